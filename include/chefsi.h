@@ -1,0 +1,210 @@
+/*
+ * chefsi.h -- C-ABI of libchefsi.so: one Chebyshev-filtered subspace iteration
+ * (CheFSI) step of real-space Kohn-Sham DFT on an AMD Instinct MI355X (gfx950).
+ *
+ * The operation is Algorithm 1 of Sharma et al., "GPU acceleration of local and
+ * semilocal density functional calculations in the SPARC electronic structure
+ * code" (arXiv:2302.09708):
+ *
+ *   Filtering        X~ = p_m((H - cI)/e) X,  c = (lam_hi + lam_cut)/2,
+ *                    e = (lam_hi - lam_cut)/2                  (Alg. 1; Sec. 2.1)
+ *   Projection       H~ = X~^T (H X~),  M~ = X~^T X~           (Alg. 1; Sec. 2.2)
+ *   Diagonalization  H~ Z~ = M~ Z~ D~                           (Alg. 1; Sec. 2.3)
+ *   Rotation         X = X~ Z~                                  (Alg. 1; Sec. 2.4)
+ *
+ * for the matrix-free Hamiltonian of Sec. 2.1,
+ *
+ *   H = -1/2 Lap_FD + diag(Veff) + sum_J chi_J diag(gamma_J) chi_J^T dV,
+ *
+ * with a central finite-difference Laplacian of even order n0 = 2r on a uniform
+ * grid, periodic or Dirichlet per direction, and Kleinman-Bylander projectors
+ * chi_J on the grid points S_J of atom J.  dV = hx*hy*hz.
+ *
+ * The filter is evaluated in its scaled three-term form: the result equals the
+ * paper's p_m((H - cI)/e) X divided by the scalar p_m((lam_lo - c)/e), which
+ * leaves every Ritz pair unchanged and keeps the iterates O(1).  "degree" m is
+ * the number of H applications inside the filter; one more gives H X~.
+ *
+ * Conventions shared by every call
+ *   - Grid point (x, y, z) has linear index i = x + Nx*(y + Ny*z).
+ *   - An orbital block X is Nd x ns, column-major with leading dimension Nd
+ *     (a row-major (ns, Nd) array whose row j is orbital j), in DEVICE memory.
+ *     Its element type is double for CHEFSI_FP64 handles and float for
+ *     CHEFSI_MIXED handles.
+ *   - `ws` is caller-owned DEVICE memory of at least chefsi_workspace_bytes()
+ *     bytes, 256-byte aligned.  Its contents on entry are ignored and on exit
+ *     are unspecified.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call enqueues
+ *     its work on that stream; calls that return host data (Ritz values)
+ *     synchronize the stream before returning.
+ *   - Every call returns a chefsi_status (0 = CHEFSI_OK).  No exception or
+ *     abort crosses the ABI.  After an error the handle stays valid, device
+ *     outputs are unspecified and nothing leaks.
+ *   - Handles are independent and thread-compatible (one handle per thread or
+ *     per request); calls on one handle must not overlap.
+ */
+#ifndef CHEFSI_H
+#define CHEFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHEFSI_OK = 0,
+  CHEFSI_ERR_INVALID_ARG = 1,  /* bad dims/order/bc, ns out of range, bad pointer, bad bounds     */
+  CHEFSI_ERR_HIP = 2,          /* a HIP runtime call failed (message in chefsi_last_error)        */
+  CHEFSI_ERR_WORKSPACE = 3,    /* ws_bytes smaller than chefsi_workspace_bytes()                   */
+  CHEFSI_ERR_NOT_POSDEF = 4,   /* Cholesky of M~ failed: filtered block is numerically rank deficient */
+  CHEFSI_ERR_EIG = 5,          /* dense eigensolver did not converge                               */
+  CHEFSI_ERR_NONFINITE = 6,    /* NaN/Inf among the Ritz values                                    */
+  CHEFSI_ERR_SOLVER = 7,       /* rocBLAS/rocSOLVER returned an error status                       */
+  CHEFSI_ERR_OOM = 8           /* a library-internal allocation failed (create only)               */
+} chefsi_status;
+
+typedef enum { CHEFSI_FP64 = 0, CHEFSI_MIXED = 1 } chefsi_precision;
+
+typedef struct chefsi_handle chefsi_handle_t;
+
+/* Uniform grid (Sec. 2.1; the grid spacing is the method's single
+ * discretisation parameter).  n[d] >= 1; in a periodic direction n[d] >= r
+ * (r = fd_order/2).  fd_order even, 2..12.  h[d] > 0 (bohr). */
+typedef struct {
+  int32_t n[3];
+  double h[3];
+  int32_t bc[3];     /* 0 = periodic, 1 = Dirichlet (zero outside nodes 0..n-1) */
+  int32_t fd_order;
+} chefsi_grid_t;
+
+/* Kleinman-Bylander projectors (Sec. 2.1, third bullet), all HOST pointers,
+ * copied by chefsi_create.  For atom J (0 <= J < n_atoms):
+ *   support  S_J = supp_idx[supp_ptr[J] .. supp_ptr[J+1])  linear grid indices,
+ *            strictly increasing within an atom;
+ *   n_J      = supp_ptr[J+1] - supp_ptr[J];
+ *   np_J     = nproj[J] >= 1 projectors;
+ *   chi_J    = the next n_J*np_J values of `chi`, column-major n_J x np_J
+ *              (projector a of atom J at support point s is chi_J[s + a*n_J]);
+ *   gamma_J  = the next np_J values of `gamma` (Ha).
+ * n_atoms = 0 means no nonlocal term (the other pointers may then be NULL). */
+typedef struct {
+  int32_t n_atoms;
+  const int64_t* supp_ptr;
+  const int32_t* supp_idx;
+  const int32_t* nproj;
+  const double* chi;
+  const double* gamma;
+} chefsi_nonlocal_t;
+
+/* Build a handle for one Hamiltonian.  Copies Veff (Nd doubles, HOST) and the
+ * projectors to library-owned device memory on the current HIP device (freed
+ * by chefsi_destroy); the caller may free its copies on return.  max_ns bounds
+ * the ns of later calls.  precision selects the element type of X and the
+ * arithmetic of filtering/projection/rotation; the dense stage is always FP64.
+ * Returns CHEFSI_ERR_INVALID_ARG on inconsistent input (including a support
+ * index outside the grid or not strictly increasing). */
+int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
+                  int32_t precision, int32_t max_ns, chefsi_handle_t** out);
+
+/* Release everything the handle owns.  NULL is ignored. */
+void chefsi_destroy(chefsi_handle_t* h);
+
+/* Exact number of workspace bytes every call below needs for block width ns
+ * (1 <= ns <= max_ns).  Writes *bytes; used for admission by memory. */
+int chefsi_workspace_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes);
+
+/* Rigorous filter bounds for the first step (the paper names lam_hi the
+ * largest eigenvalue of H and lam_cut the cutoff, Alg. 1, but does not say how
+ * they are obtained; these are this library's reading):
+ *   lam_hi  = 1/2 sum_d sum_{|p|<=r} |w_p|/h_d^2 + max Veff
+ *             + max_i sum_{(J,a) touching i} |gamma_Ja| |chi_Ja(i)| ||chi_Ja||_1 dV   (Gershgorin)
+ *   lam_lo  = min Veff (minus the nonlocal bound if some gamma < 0)
+ *   lam_cut = lam_lo + 0.1 (lam_hi - lam_lo).
+ * Host arithmetic only; any output pointer may be NULL. */
+int chefsi_spectral_bounds(const chefsi_handle_t* h, double* lam_lo, double* lam_cut, double* lam_hi);
+
+/* Y = H X for an Nd x ns block (Sec. 2.1: stencil + Veff + nonlocal).  X and Y
+ * are distinct device blocks of the handle's element type. */
+int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* X <- scaled Chebyshev filter of degree m >= 1 applied to X, in place
+ * (Alg. 1, Filtering).  Requires lam_lo < lam_cut < lam_hi. */
+int chefsi_filter(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree,
+                  double lam_lo, double lam_cut, double lam_hi,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Projection (Alg. 1; Sec. 2.2): Hs = X^T (H X) and Ms = X^T X for the
+ * filtered block X, written as full symmetric ns x ns column-major FP64
+ * matrices to the device arrays Hs and Ms (leading dimension ns). */
+int chefsi_project(chefsi_handle_t* h, const void* X, int32_t ns, double* Hs, double* Ms,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Subspace diagonalization (Alg. 1; Sec. 2.3): solve Hs Z = Ms Z D in FP64 on
+ * the device.  Hs and Ms (device, ns x ns, ld ns, symmetric; upper triangles
+ * read) are overwritten: Hs by Z (Z^T Ms Z = I, columns ordered by ascending
+ * D), Ms by its Cholesky factor.  D (device, ns doubles) gets the eigenvalues
+ * in ascending order.  CHEFSI_ERR_NOT_POSDEF if Ms is not positive definite. */
+int chefsi_eigh(chefsi_handle_t* h, double* Hs, double* Ms, double* D, int32_t ns,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Rotation (Alg. 1; Sec. 2.4): X <- X Z for a device ns x ns FP64 matrix Z
+ * (column-major, ld ns), in place. */
+int chefsi_rotate(chefsi_handle_t* h, void* X, const double* Z, int32_t ns,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* One whole CheFSI step (Alg. 1): filter, project, diagonalize, rotate.  X is
+ * updated in place to the rotated block X~ Z~ (orthonormal columns, ordered by
+ * ascending Ritz value); ritz_host (HOST, ns doubles) receives D~.  Returns
+ * CHEFSI_ERR_NONFINITE if a Ritz value is not finite. */
+int chefsi_step(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree,
+                double lam_lo, double lam_cut, double lam_hi,
+                void* ws, size_t ws_bytes, void* stream, double* ritz_host);
+
+/* n_iter >= 1 CheFSI steps from X with the bounds update used between SCF
+ * iterations by this library (a reading; the paper fixes none):
+ * lam_lo <- D_1 and lam_cut <- D_ns after every step, lam_hi fixed.
+ * ritz_host receives the last step's D~.  The final bounds are written to
+ * *lam_lo_out / *lam_cut_out when those are not NULL. */
+int chefsi_solve(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, int32_t n_iter,
+                 double lam_lo, double lam_cut, double lam_hi,
+                 void* ws, size_t ws_bytes, void* stream, double* ritz_host,
+                 double* lam_lo_out, double* lam_cut_out);
+
+/* Final FP64 Rayleigh-Ritz pass for a CHEFSI_MIXED handle (X is FP32): forms
+ * Hs = X^T (H X) and Ms = X^T X with FP64 arithmetic from the FP32 block,
+ * solves the FP64 subspace problem, rotates X in FP64 (stored back as FP32)
+ * and returns the FP64 Ritz values.  On a CHEFSI_FP64 handle it is one
+ * Rayleigh-Ritz pass with no filtering. */
+int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns,
+                       void* ws, size_t ws_bytes, void* stream, double* ritz_host);
+
+/* Per-kernel timing with HIP events recorded on the call's stream around every
+ * launch of the named kernel (off by default; enabling it adds event records
+ * but changes no result).  kernel ids: 0 hx_apply, 1 nl_project, 2 gram,
+ * 3 gram_reduce, 4 rotate, 5 dense eigensolve (whole FP64 stage), 6 copy.
+ * chefsi_profile_read synchronizes on the recorded events and returns the
+ * summed milliseconds and launch count since the last reset. */
+int chefsi_profile_enable(chefsi_handle_t* h, int32_t on);
+int chefsi_profile_reset(chefsi_handle_t* h);
+int chefsi_profile_read(chefsi_handle_t* h, int32_t kernel_id, double* total_ms, int64_t* launches);
+
+/* Status of the last failing call on this handle: for NOT_POSDEF the
+ * rocSOLVER info value (order of the failing leading minor + ns), else 0. */
+int chefsi_last_info(const chefsi_handle_t* h);
+
+/* Static description of a status code, and the last error message recorded on
+ * a handle (never NULL; empty if none). */
+const char* chefsi_strerror(int status);
+const char* chefsi_last_error(const chefsi_handle_t* h);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int chefsi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEFSI_H */

@@ -1,0 +1,261 @@
+"""ctypes binding of libchefsi.so (include/chefsi.h): argument marshalling only.
+
+Every step of the CheFSI path runs in the library's HIP kernels and rocSOLVER;
+this module only converts Python/NumPy/torch arguments to the C-ABI's plain
+pointers and sizes and turns non-zero status codes into ``ChefsiError``.
+Device blocks are torch tensors on a ROCm device (torch supplies device memory
+and streams).  If the library is missing, loading fails loudly: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchefsi.so")
+
+FP64 = 0
+MIXED = 1
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_HIP = 2
+ERR_WORKSPACE = 3
+ERR_NOT_POSDEF = 4
+ERR_EIG = 5
+ERR_NONFINITE = 6
+ERR_SOLVER = 7
+ERR_OOM = 8
+
+PROF_HX, PROF_NL, PROF_GRAM, PROF_REDUCE, PROF_ROT, PROF_EIG, PROF_COPY = range(7)
+
+# every symbol include/chefsi.h declares
+EXPORTS = (
+    "chefsi_create", "chefsi_destroy", "chefsi_workspace_bytes", "chefsi_spectral_bounds",
+    "chefsi_apply_h", "chefsi_filter", "chefsi_project", "chefsi_eigh", "chefsi_rotate",
+    "chefsi_step", "chefsi_solve", "chefsi_refine_fp64", "chefsi_profile_enable",
+    "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
+    "chefsi_last_error", "chefsi_version",
+)
+
+
+class ChefsiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"chefsi status {status}: {message}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double * 3), ("bc", C.c_int32 * 3), ("fd_order", C.c_int32)]
+
+
+class Nonlocal(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32),
+                ("supp_ptr", C.POINTER(C.c_int64)),
+                ("supp_idx", C.POINTER(C.c_int32)),
+                ("nproj", C.POINTER(C.c_int32)),
+                ("chi", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libchefsi.so and declare its signatures.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2302_09708_amd.build`")
+    lib = C.CDLL(path)
+    vp, sz, i32, dbl = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
+    pd = C.POINTER(C.c_double)
+    lib.chefsi_create.argtypes = [C.POINTER(Grid), pd, C.POINTER(Nonlocal), i32, i32, C.POINTER(vp)]
+    lib.chefsi_destroy.argtypes = [vp]
+    lib.chefsi_destroy.restype = None
+    lib.chefsi_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
+    lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
+    lib.chefsi_project.argtypes = [vp, vp, i32, vp, vp, vp, sz, vp]
+    lib.chefsi_eigh.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_rotate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_step.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd]
+    lib.chefsi_solve.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd, pd, pd]
+    lib.chefsi_refine_fp64.argtypes = [vp, vp, i32, vp, sz, vp, pd]
+    lib.chefsi_profile_enable.argtypes = [vp, i32]
+    lib.chefsi_profile_reset.argtypes = [vp]
+    lib.chefsi_profile_read.argtypes = [vp, i32, pd, C.POINTER(C.c_int64)]
+    lib.chefsi_last_info.argtypes = [vp]
+    lib.chefsi_strerror.argtypes = [C.c_int]
+    lib.chefsi_strerror.restype = C.c_char_p
+    lib.chefsi_last_error.argtypes = [vp]
+    lib.chefsi_last_error.restype = C.c_char_p
+    lib.chefsi_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Handle:
+    """One Hamiltonian on the current device (chefsi_create / chefsi_destroy)."""
+
+    def __init__(self, problem, precision: int = FP64, max_ns: int = 1):
+        lib = load()
+        self._lib = lib
+        g = Grid()
+        for d in range(3):
+            g.n[d] = int(problem.n[d])
+            g.h[d] = float(problem.h[d])
+            g.bc[d] = int(problem.bc[d])
+        g.fd_order = int(problem.fd_order)
+        self._keep = []
+        veff = np.ascontiguousarray(problem.veff, dtype=np.float64)
+        self._keep.append(veff)
+        nl = Nonlocal()
+        nl.n_atoms = int(len(problem.nproj))
+        if nl.n_atoms > 0:
+            arrs = [np.ascontiguousarray(problem.supp_ptr, dtype=np.int64),
+                    np.ascontiguousarray(problem.supp_idx, dtype=np.int32),
+                    np.ascontiguousarray(problem.nproj, dtype=np.int32),
+                    np.ascontiguousarray(problem.chi, dtype=np.float64),
+                    np.ascontiguousarray(problem.gamma, dtype=np.float64)]
+            self._keep += arrs
+            nl.supp_ptr = arrs[0].ctypes.data_as(C.POINTER(C.c_int64))
+            nl.supp_idx = arrs[1].ctypes.data_as(C.POINTER(C.c_int32))
+            nl.nproj = arrs[2].ctypes.data_as(C.POINTER(C.c_int32))
+            nl.chi = arrs[3].ctypes.data_as(C.POINTER(C.c_double))
+            nl.gamma = arrs[4].ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        st = lib.chefsi_create(C.byref(g), veff.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nl),
+                               int(precision), int(max_ns), C.byref(h))
+        self._keep = []
+        if st != OK:
+            raise ChefsiError(st, lib.chefsi_strerror(st).decode())
+        self.h = h
+        self.precision = precision
+        self.nd = int(np.prod(problem.n))
+        self.max_ns = int(max_ns)
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st: int):
+        if st != OK:
+            msg = self._lib.chefsi_last_error(self.h).decode() or self._lib.chefsi_strerror(st).decode()
+            raise ChefsiError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.chefsi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C-ABI calls -------------------------------------------------------------
+    def chefsi_workspace_bytes(self, ns: int) -> int:
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_workspace_bytes(self.h, int(ns), C.byref(b)))
+        return int(b.value)
+
+    def chefsi_spectral_bounds(self) -> Tuple[float, float, float]:
+        lo, cut, hi = C.c_double(), C.c_double(), C.c_double()
+        self._check(self._lib.chefsi_spectral_bounds(self.h, C.byref(lo), C.byref(cut), C.byref(hi)))
+        return lo.value, cut.value, hi.value
+
+    def chefsi_apply_h(self, X, Y, ns, ws, ws_bytes=None, stream=None):
+        self._check(self._lib.chefsi_apply_h(self.h, _ptr(X), _ptr(Y), int(ns), _ptr(ws),
+                                             self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_filter(self, X, ns, degree, lam_lo, lam_cut, lam_hi, ws, ws_bytes=None, stream=None):
+        self._check(self._lib.chefsi_filter(self.h, _ptr(X), int(ns), int(degree), float(lam_lo), float(lam_cut),
+                                            float(lam_hi), _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_project(self, X, ns, Hs, Ms, ws, ws_bytes=None, stream=None):
+        self._check(self._lib.chefsi_project(self.h, _ptr(X), int(ns), _ptr(Hs), _ptr(Ms), _ptr(ws),
+                                             self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_eigh(self, Hs, Ms, D, ns, ws, ws_bytes=None, stream=None):
+        self._check(self._lib.chefsi_eigh(self.h, _ptr(Hs), _ptr(Ms), _ptr(D), int(ns), _ptr(ws),
+                                          self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_rotate(self, X, Z, ns, ws, ws_bytes=None, stream=None):
+        self._check(self._lib.chefsi_rotate(self.h, _ptr(X), _ptr(Z), int(ns), _ptr(ws),
+                                            self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_step(self, X, ns, degree, lam_lo, lam_cut, lam_hi, ws, ws_bytes=None, stream=None) -> np.ndarray:
+        ritz = np.zeros(int(ns))
+        self._check(self._lib.chefsi_step(self.h, _ptr(X), int(ns), int(degree), float(lam_lo), float(lam_cut),
+                                          float(lam_hi), _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream),
+                                          ritz.ctypes.data_as(C.POINTER(C.c_double))))
+        return ritz
+
+    def chefsi_solve(self, X, ns, degree, n_iter, lam_lo, lam_cut, lam_hi, ws, ws_bytes=None, stream=None):
+        ritz = np.zeros(int(ns))
+        lo, cut = C.c_double(), C.c_double()
+        self._check(self._lib.chefsi_solve(self.h, _ptr(X), int(ns), int(degree), int(n_iter), float(lam_lo),
+                                           float(lam_cut), float(lam_hi), _ptr(ws), self._wsb(ws, ws_bytes),
+                                           _stream(stream), ritz.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.byref(lo), C.byref(cut)))
+        return ritz, lo.value, cut.value
+
+    def chefsi_refine_fp64(self, X, ns, ws, ws_bytes=None, stream=None) -> np.ndarray:
+        ritz = np.zeros(int(ns))
+        self._check(self._lib.chefsi_refine_fp64(self.h, _ptr(X), int(ns), _ptr(ws), self._wsb(ws, ws_bytes),
+                                                 _stream(stream), ritz.ctypes.data_as(C.POINTER(C.c_double))))
+        return ritz
+
+    def chefsi_profile_enable(self, on: bool = True):
+        self._check(self._lib.chefsi_profile_enable(self.h, 1 if on else 0))
+
+    def chefsi_profile_reset(self):
+        self._check(self._lib.chefsi_profile_reset(self.h))
+
+    def chefsi_profile_read(self, kernel_id: int) -> Tuple[float, int]:
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self._lib.chefsi_profile_read(self.h, int(kernel_id), C.byref(ms), C.byref(n)))
+        return ms.value, int(n.value)
+
+    def chefsi_last_info(self) -> int:
+        return int(self._lib.chefsi_last_info(self.h))
+
+    @staticmethod
+    def _wsb(ws, ws_bytes: Optional[int]) -> int:
+        if ws_bytes is not None:
+            return int(ws_bytes)
+        return int(ws.numel() * ws.element_size())
+
+
+def workspace(handle: Handle, ns: int, device=None):
+    """A torch uint8 device buffer of exactly chefsi_workspace_bytes(ns) bytes (caching allocator: 512-B aligned)."""
+    import torch
+    nbytes = handle.chefsi_workspace_bytes(ns)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def strerror(status: int) -> str:
+    return load().chefsi_strerror(int(status)).decode()

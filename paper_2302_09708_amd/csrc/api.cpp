@@ -1,0 +1,951 @@
+// Host runtime of libchefsi: handle, validation, workspace plan, CheFSI step orchestration,
+// FP64 dense stage (rocSOLVER) and the C-ABI declared in include/chefsi.h.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/chefsi.h"
+#include "common.h"
+
+using namespace chefsi;
+
+namespace {
+
+constexpr int kNumProf = 7;
+enum ProfId { P_HX = 0, P_NL = 1, P_GRAM = 2, P_REDUCE = 3, P_ROT = 4, P_EIG = 5, P_COPY = 6 };
+
+struct Error {
+  int status;
+  std::string msg;
+};
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) throw Error{CHEFSI_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define BLAS_TRY(expr)                                                                         \
+  do {                                                                                         \
+    rocblas_status s_ = (expr);                                                                \
+    if (s_ != rocblas_status_success)                                                          \
+      throw Error{CHEFSI_ERR_SOLVER, std::string(#expr) + ": " + rocblas_status_to_string(s_)}; \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Central second-derivative weights of even order 2r (closed form of the
+// Lagrange-interpolation stencil); Sec. 2.1 names only the order n0.
+std::vector<double> fd_weights(int order) {
+  const int r = order / 2;
+  std::vector<double> w(r + 1, 0.0);
+  long double s = 0.0L;
+  for (int p = 1; p <= r; ++p) s += 1.0L / ((long double)p * p);
+  w[0] = (double)(-2.0L * s);
+  auto fact = [](int n) {
+    long double f = 1.0L;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+  };
+  for (int p = 1; p <= r; ++p) {
+    long double num = 2.0L * fact(r) * fact(r);
+    long double den = (long double)p * p * fact(r - p) * fact(r + p);
+    w[p] = (double)((p % 2 ? 1.0L : -1.0L) * num / den);
+  }
+  return w;
+}
+
+struct EventPair {
+  int id;
+  hipEvent_t b, e;
+};
+
+}  // namespace
+
+struct chefsi_handle {
+  int device = 0;
+  int precision = CHEFSI_FP64;
+  int n[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0};
+  int order = 12, radius = 6;
+  int64_t nd = 0;
+  int max_ns = 0;
+  double dv = 0.0;
+  std::vector<double> w;
+
+  // host copies kept for the spectral bounds
+  std::vector<double> veff_h;
+  int n_atoms = 0;
+  int np_tot = 0;
+  std::vector<int64_t> supp_ptr_h;
+  std::vector<int> supp_idx_h, nproj_h;
+  std::vector<double> chi_h, gamma_h;
+
+  // device data
+  double* veff64 = nullptr;
+  float* veff32 = nullptr;
+  int* supp_off = nullptr;
+  int* supp_idx = nullptr;
+  int64_t* chi_off = nullptr;
+  int* nproj = nullptr;
+  int* poff = nullptr;
+  double* chi64 = nullptr;
+  float* chi32 = nullptr;
+  double* gdv64 = nullptr;
+  float* gdv32 = nullptr;
+  int* nl_row = nullptr;
+  int* nl_proj = nullptr;
+  double* nl_val64 = nullptr;
+  float* nl_val32 = nullptr;
+
+  rocblas_handle blas = nullptr;
+  std::map<int, size_t> solver_ws_cache;
+  int py_override = 0;
+
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<EventPair> ev_pending;
+  double prof_ms[kNumProf] = {0};
+  int64_t prof_n[kNumProf] = {0};
+
+  int last_info = 0;
+  std::string last_error;
+};
+
+namespace {
+
+struct WsLayout {
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, partial = 0, solver = 0, total = 0;
+  size_t bufB_bytes = 0, solver_bytes = 0;
+  GramPlan gram;
+};
+
+size_t elem_bytes(const chefsi_handle* h) { return h->precision == CHEFSI_FP64 ? 8 : 4; }
+
+size_t solver_workspace(chefsi_handle* h, int ns) {
+  auto it = h->solver_ws_cache.find(ns);
+  if (it != h->solver_ws_cache.end()) return it->second;
+  size_t sz = 0;
+  BLAS_TRY(rocblas_start_device_memory_size_query(h->blas));
+  rocsolver_dsygvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr,
+                   ns, nullptr, nullptr, nullptr);
+  BLAS_TRY(rocblas_stop_device_memory_size_query(h->blas, &sz));
+  h->solver_ws_cache[ns] = sz;
+  return sz;
+}
+
+WsLayout layout(chefsi_handle* h, int ns) {
+  WsLayout L;
+  size_t off = 0;
+  L.bufB = off;
+  // mixed handles need an FP64 Nd x ns scratch for the FP64 Rayleigh-Ritz pass: same bytes as FP64 X
+  L.bufB_bytes = (size_t)h->nd * ns * 8;
+  off += align256(L.bufB_bytes);
+  L.alpha = off;
+  off += align256((size_t)std::max(1, h->np_tot) * ns * 8);
+  L.hs = off;
+  off += align256((size_t)ns * ns * 8);
+  L.ms = off;
+  off += align256((size_t)ns * ns * 8);
+  L.d = off;
+  off += align256((size_t)ns * 8);
+  L.e = off;
+  off += align256((size_t)ns * 8);
+  L.info = off;
+  off += 256;
+  L.gram = plan_gram(h->nd, ns);
+  L.partial = off;
+  off += align256(L.gram.partial_bytes);
+  L.solver = off;
+  L.solver_bytes = solver_workspace(h, ns);
+  off += align256(std::max<size_t>(L.solver_bytes, 256));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// ---- profiling -------------------------------------------------------------
+struct ProfScope {
+  chefsi_handle* h;
+  hipStream_t s;
+  int id;
+  hipEvent_t b = nullptr, e = nullptr;
+  ProfScope(chefsi_handle* h_, int id_, hipStream_t s_) : h(h_), s(s_), id(id_) {
+    if (!h->prof_on) return;
+    b = take();
+    e = take();
+    HIP_TRY(hipEventRecord(b, s));
+  }
+  hipEvent_t take() {
+    if (!h->ev_pool.empty()) {
+      hipEvent_t ev = h->ev_pool.back();
+      h->ev_pool.pop_back();
+      return ev;
+    }
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreate(&ev));
+    return ev;
+  }
+  void done() {
+    if (!h->prof_on || b == nullptr) return;
+    HIP_TRY(hipEventRecord(e, s));
+    h->ev_pending.push_back({id, b, e});
+    b = e = nullptr;
+  }
+  ~ProfScope() {
+    if (b) h->ev_pool.push_back(b);
+    if (e) h->ev_pool.push_back(e);
+  }
+};
+
+void prof_collect(chefsi_handle* h) {
+  for (auto& p : h->ev_pending) {
+    HIP_TRY(hipEventSynchronize(p.e));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.b, p.e));
+    h->prof_ms[p.id] += ms;
+    h->prof_n[p.id] += 1;
+    h->ev_pool.push_back(p.b);
+    h->ev_pool.push_back(p.e);
+  }
+  h->ev_pending.clear();
+}
+
+// ---- argument checks -------------------------------------------------------
+void check(bool ok, const char* what) {
+  if (!ok) throw Error{CHEFSI_ERR_INVALID_ARG, what};
+}
+
+void check_ns(const chefsi_handle* h, int ns) {
+  check(ns >= 1 && ns <= h->max_ns, "ns must satisfy 1 <= ns <= max_ns");
+  check((int64_t)ns <= h->nd, "ns must not exceed Nd");
+}
+
+void check_ws(chefsi_handle* h, int ns, void* ws, size_t ws_bytes, WsLayout& L) {
+  L = layout(h, ns);
+  if (ws == nullptr || ws_bytes < L.total)
+    throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_workspace_bytes(ns)"};
+  check(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
+}
+
+void check_bounds(double lo, double cut, double hi) {
+  check(std::isfinite(lo) && std::isfinite(cut) && std::isfinite(hi), "spectral bounds must be finite");
+  check(lo <= cut && cut < hi, "bounds must satisfy lam_lo <= lam_cut < lam_hi");
+}
+
+// ---- kernel wrappers -------------------------------------------------------
+template <typename TI, typename TC, typename TO>
+HxArgs<TI, TC, TO> hx_args(const chefsi_handle* h, const TI* x, const TO* prev, TO* out, const TC* veff,
+                           const TC* nl_val, const TC* alpha) {
+  HxArgs<TI, TC, TO> a{};
+  a.x = x;
+  a.prev = prev;
+  a.out = out;
+  a.veff = veff;
+  a.nl_row = h->np_tot > 0 ? h->nl_row : nullptr;
+  a.nl_proj = h->nl_proj;
+  a.nl_val = nl_val;
+  a.alpha = alpha;
+  a.np_tot = h->np_tot;
+  a.nx = h->n[0];
+  a.ny = h->n[1];
+  a.nz = h->n[2];
+  a.nd = h->nd;
+  a.per_x = h->bc[0] == 0;
+  a.per_y = h->bc[1] == 0;
+  a.per_z = h->bc[2] == 0;
+  double sumh = 0.0;
+  for (int d = 0; d < 3; ++d) sumh += 1.0 / (h->h[d] * h->h[d]);
+  a.c0 = TC(-0.5 * h->w[0] * sumh);
+  for (int p = 0; p <= kMaxRadius; ++p) {
+    const double wp = p <= h->radius ? h->w[p] : 0.0;
+    a.cx[p] = TC(-0.5 * wp / (h->h[0] * h->h[0]));
+    a.cy[p] = TC(-0.5 * wp / (h->h[1] * h->h[1]));
+    a.cz[p] = TC(-0.5 * wp / (h->h[2] * h->h[2]));
+  }
+  a.sa = TC(1);
+  a.sc = TC(0);
+  a.sb = TC(0);
+  return a;
+}
+
+template <typename TI, typename TC>
+NlArgs<TI, TC> nl_args(const chefsi_handle* h, const TI* y, int ns, const TC* chi, const TC* gdv, TC* alpha) {
+  NlArgs<TI, TC> a{};
+  a.y = y;
+  a.nd = h->nd;
+  a.ns = ns;
+  a.n_atoms = h->n_atoms;
+  a.supp_off = h->supp_off;
+  a.supp_idx = h->supp_idx;
+  a.chi_off = h->chi_off;
+  a.nproj = h->nproj;
+  a.poff = h->poff;
+  a.chi = chi;
+  a.gdv = gdv;
+  a.alpha = alpha;
+  a.np_tot = h->np_tot;
+  return a;
+}
+
+// out = sa (H x - sc x) + sb prev, with the projector gather for x first.
+template <typename TI, typename TC, typename TO>
+void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns, double sa, double sc, double sb,
+                 TC* alpha, hipStream_t s) {
+  const TC* veff;
+  const TC* nlv;
+  const TC* chi;
+  const TC* gdv;
+  if constexpr (sizeof(TC) == 8) {
+    veff = h->veff64;
+    nlv = h->nl_val64;
+    chi = h->chi64;
+    gdv = h->gdv64;
+  } else {
+    veff = h->veff32;
+    nlv = h->nl_val32;
+    chi = h->chi32;
+    gdv = h->gdv32;
+  }
+  if (h->np_tot > 0) {
+    ProfScope ps(h, P_NL, s);
+    HIP_TRY((launch_nl_project<TI, TC>(nl_args<TI, TC>(h, x, ns, chi, gdv, alpha), s)));
+    ps.done();
+  }
+  auto a = hx_args<TI, TC, TO>(h, x, prev, out, veff, nlv, alpha);
+  a.sa = TC(sa);
+  a.sc = TC(sc);
+  a.sb = TC(sb);
+  const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->py_override);
+  a.nyg = p.nyg;
+  a.ty = p.ty;
+  a.nty = p.nty;
+  a.zc = p.zc;
+  ProfScope ps(h, P_HX, s);
+  HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
+  ps.done();
+}
+
+// Scaled Chebyshev filter (Alg. 1, Filtering).  Y_0 = X in buffer A; Y_{k+1} overwrites Y_{k-1}.
+// Returns the buffer that holds Y_m (A when m is even, B when odd).
+template <typename T>
+T* run_filter(chefsi_handle* h, T* A, T* B, int ns, int m, double lo, double cut, double hi, T* alpha,
+              hipStream_t s) {
+  const double c = 0.5 * (hi + cut);
+  const double e = 0.5 * (hi - cut);
+  const double s1 = e / (lo - c);
+  double sig = s1;
+  // Y_1 = (s1 / e)(H - c) Y_0
+  apply_fused<T, T, T>(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s);
+  T* cur = B;
+  T* other = A;
+  for (int k = 1; k < m; ++k) {
+    const double sig_next = 1.0 / (2.0 / s1 - sig);
+    apply_fused<T, T, T>(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s);
+    std::swap(cur, other);
+    sig = sig_next;
+  }
+  return cur;
+}
+
+// Hs = X^T Y, Ms = X^T X (full symmetric, FP64), via split-K partial tiles.
+template <typename TX, typename TY>
+void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayout& L, void* ws, double* Hs,
+               double* Ms, hipStream_t s) {
+  double* part = at<double>(ws, L.partial);
+  {
+    ProfScope ps(h, P_GRAM, s);
+    HIP_TRY((launch_gram_f64<TX, TY>(X, Y, h->nd, ns, L.gram, part, s)));
+    ps.done();
+  }
+  {
+    ProfScope ps(h, P_REDUCE, s);
+    HIP_TRY(launch_gram_reduce(part, L.gram, ns, Hs, s));
+    ps.done();
+  }
+  {
+    ProfScope ps(h, P_GRAM, s);
+    HIP_TRY((launch_gram_f64<TX, TX>(X, X, h->nd, ns, L.gram, part, s)));
+    ps.done();
+  }
+  {
+    ProfScope ps(h, P_REDUCE, s);
+    HIP_TRY(launch_gram_reduce(part, L.gram, ns, Ms, s));
+    ps.done();
+  }
+}
+
+// Hs Z = Ms Z D in FP64 on the device (rocSOLVER dsygvd: Cholesky, reduction, divide and conquer).
+void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
+               hipStream_t s) {
+  ProfScope ps(h, P_EIG, s);
+  BLAS_TRY(rocblas_set_stream(h->blas, s));
+  BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+  rocblas_int* info = at<rocblas_int>(ws, L.info);
+  BLAS_TRY(rocsolver_dsygvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, Hs, ns, Ms, ns,
+                            D, at<double>(ws, L.e), info));
+  ps.done();
+}
+
+void check_info(chefsi_handle* h, void* ws, const WsLayout& L, int ns, hipStream_t s) {
+  rocblas_int info = 0;
+  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (info > ns) {
+    h->last_info = info;
+    throw Error{CHEFSI_ERR_NOT_POSDEF, "Cholesky of the overlap matrix failed (leading minor " +
+                                           std::to_string(info - ns) + ")"};
+  }
+  if (info > 0) {
+    h->last_info = info;
+    throw Error{CHEFSI_ERR_EIG, "dense eigensolver did not converge"};
+  }
+}
+
+template <typename T>
+void copy_block(chefsi_handle* h, T* dst, const T* src, int ns, hipStream_t s) {
+  ProfScope ps(h, P_COPY, s);
+  HIP_TRY(hipMemcpyAsync(dst, src, (size_t)h->nd * ns * sizeof(T), hipMemcpyDeviceToDevice, s));
+  ps.done();
+}
+
+template <typename T>
+void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hipStream_t s) {
+  ProfScope ps(h, P_ROT, s);
+  HIP_TRY((launch_rotate_f64<T, T>(X, Z, O, h->nd, ns, s)));
+  ps.done();
+}
+
+void ritz_to_host(chefsi_handle* h, const double* D, int ns, double* ritz_host, void* ws, const WsLayout& L,
+                  hipStream_t s) {
+  rocblas_int info = 0;
+  std::vector<double> d(ns);
+  HIP_TRY(hipMemcpyAsync(d.data(), D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (info > ns) {
+    h->last_info = info;
+    throw Error{CHEFSI_ERR_NOT_POSDEF, "Cholesky of the overlap matrix failed"};
+  }
+  if (info > 0) {
+    h->last_info = info;
+    throw Error{CHEFSI_ERR_EIG, "dense eigensolver did not converge"};
+  }
+  for (int i = 0; i < ns; ++i)
+    if (!std::isfinite(d[i])) throw Error{CHEFSI_ERR_NONFINITE, "non-finite Ritz value"};
+  if (ritz_host) std::memcpy(ritz_host, d.data(), (size_t)ns * 8);
+}
+
+// One CheFSI step (Alg. 1) for element type T (double: FP64 handle, float: mixed handle).
+template <typename T>
+void step_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, double hi, void* ws,
+               const WsLayout& L, hipStream_t s, double* ritz_host) {
+  T* A = X;
+  T* B = at<T>(ws, L.bufB);
+  T* alpha = at<T>(ws, L.alpha);
+  double* Hs = at<double>(ws, L.hs);
+  double* Ms = at<double>(ws, L.ms);
+  double* D = at<double>(ws, L.d);
+  T* Xf = run_filter<T>(h, A, B, ns, m, lo, cut, hi, alpha, s);
+  T* Yf = Xf == A ? B : A;
+  apply_fused<T, T, T>(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
+  gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s);
+  dense_eig(h, Hs, Ms, D, ns, L, ws, s);
+  rotate_into<T>(h, Xf, Hs, Yf, ns, s);  // Y~ is dead: X = X~ Z~ goes there
+  if (Yf != X) copy_block<T>(h, X, Yf, ns, s);
+  ritz_to_host(h, D, ns, ritz_host, ws, L, s);
+}
+
+// FP64 Rayleigh-Ritz on the block X (no filter): FP64 arithmetic whatever the storage type.
+template <typename T>
+void refine_impl(chefsi_handle* h, T* X, int ns, void* ws, const WsLayout& L, hipStream_t s, double* ritz_host) {
+  double* HX = at<double>(ws, L.bufB);  // Nd x ns FP64
+  double* alpha = at<double>(ws, L.alpha);
+  double* Hs = at<double>(ws, L.hs);
+  double* Ms = at<double>(ws, L.ms);
+  double* D = at<double>(ws, L.d);
+  apply_fused<T, double, double>(h, X, nullptr, HX, ns, 1.0, 0.0, 0.0, alpha, s);
+  gram_pair<T, double>(h, X, HX, ns, L, ws, Hs, Ms, s);
+  dense_eig(h, Hs, Ms, D, ns, L, ws, s);
+  T* B = at<T>(ws, L.bufB);
+  rotate_into<T>(h, X, Hs, B, ns, s);
+  copy_block<T>(h, X, B, ns, s);
+  ritz_to_host(h, D, ns, ritz_host, ws, L, s);
+}
+
+int fail(chefsi_handle* h, const Error& e) {
+  if (h) h->last_error = e.msg;
+  return e.status;
+}
+
+template <typename F>
+int guarded(chefsi_handle* h, F&& f) {
+  if (h == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  try {
+    h->last_error.clear();
+    h->last_info = 0;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) HIP_TRY(hipSetDevice(h->device));
+    f();
+    return CHEFSI_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    return fail(h, Error{CHEFSI_ERR_OOM, "host allocation failed"});
+  } catch (...) {
+    return fail(h, Error{CHEFSI_ERR_HIP, "unexpected exception"});
+  }
+}
+
+template <typename T>
+T* upload(const T* src, size_t n) {
+  T* d = nullptr;
+  if (n == 0) return nullptr;
+  if (hipMalloc(&d, n * sizeof(T)) != hipSuccess) throw Error{CHEFSI_ERR_OOM, "device allocation failed"};
+  hipError_t e = hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    throw Error{CHEFSI_ERR_HIP, std::string("upload: ") + hipGetErrorString(e)};
+  }
+  return d;
+}
+
+void release(chefsi_handle* h) {
+  void* ptrs[] = {h->veff64, h->veff32, h->supp_off, h->supp_idx, h->chi_off,  h->nproj,    h->poff,
+                  h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->nl_row,   h->nl_proj,  h->nl_val64,
+                  h->nl_val32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& p : h->ev_pending) {
+    (void)hipEventDestroy(p.b);
+    (void)hipEventDestroy(p.e);
+  }
+  for (auto ev : h->ev_pool) (void)hipEventDestroy(ev);
+  if (h->blas) rocblas_destroy_handle(h->blas);
+}
+
+}  // namespace
+
+extern "C" {
+
+int chefsi_version(void) { return 100; }
+
+const char* chefsi_strerror(int status) {
+  switch (status) {
+    case CHEFSI_OK: return "ok";
+    case CHEFSI_ERR_INVALID_ARG: return "invalid argument";
+    case CHEFSI_ERR_HIP: return "HIP runtime error";
+    case CHEFSI_ERR_WORKSPACE: return "workspace too small";
+    case CHEFSI_ERR_NOT_POSDEF: return "overlap matrix not positive definite";
+    case CHEFSI_ERR_EIG: return "dense eigensolver did not converge";
+    case CHEFSI_ERR_NONFINITE: return "non-finite Ritz value";
+    case CHEFSI_ERR_SOLVER: return "rocBLAS/rocSOLVER error";
+    case CHEFSI_ERR_OOM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+const char* chefsi_last_error(const chefsi_handle_t* h) { return h ? h->last_error.c_str() : ""; }
+
+int chefsi_last_info(const chefsi_handle_t* h) { return h ? h->last_info : 0; }
+
+int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
+                  int32_t precision, int32_t max_ns, chefsi_handle_t** out) {
+  if (out == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (grid == nullptr || veff_host == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  chefsi_handle* h = nullptr;
+  try {
+    h = new chefsi_handle();
+  } catch (...) {
+    return CHEFSI_ERR_OOM;
+  }
+  try {
+    check(precision == CHEFSI_FP64 || precision == CHEFSI_MIXED, "precision must be CHEFSI_FP64 or CHEFSI_MIXED");
+    check(grid->fd_order >= 2 && grid->fd_order <= 12 && grid->fd_order % 2 == 0, "fd_order must be even, 2..12");
+    h->precision = precision;
+    h->order = grid->fd_order;
+    h->radius = grid->fd_order / 2;
+    int64_t nd = 1;
+    for (int d = 0; d < 3; ++d) {
+      check(grid->n[d] >= 1, "grid sizes must be >= 1");
+      check(grid->bc[d] == 0 || grid->bc[d] == 1, "bc must be 0 (periodic) or 1 (Dirichlet)");
+      check(std::isfinite(grid->h[d]) && grid->h[d] > 0.0, "grid spacing must be positive");
+      if (grid->bc[d] == 0) check(grid->n[d] >= h->radius, "periodic direction needs n >= fd_order/2");
+      h->n[d] = grid->n[d];
+      h->h[d] = grid->h[d];
+      h->bc[d] = grid->bc[d];
+      nd *= grid->n[d];
+    }
+    check(nd < (int64_t)1 << 31, "Nd must be below 2^31");
+    check(grid->n[0] <= kHxMaxThreads, "nx above 512 is not supported by the stencil tiling");
+    check(max_ns >= 1 && (int64_t)max_ns <= nd, "max_ns must satisfy 1 <= max_ns <= Nd");
+    for (int eb : {4, 8})
+      check(plan_hx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2, eb, 0).ok,
+            "grid too wide in x for the stencil tiling (needs 2r*nx <= 4*blocksize)");
+    h->nd = nd;
+    h->max_ns = max_ns;
+    h->dv = grid->h[0] * grid->h[1] * grid->h[2];
+    h->w = fd_weights(h->order);
+    h->veff_h.assign(veff_host, veff_host + nd);
+    for (double v : h->veff_h) check(std::isfinite(v), "Veff must be finite");
+
+    // projectors
+    if (nl != nullptr && nl->n_atoms > 0) {
+      check(nl->supp_ptr && nl->supp_idx && nl->nproj && nl->chi && nl->gamma, "null projector array");
+      const int na = nl->n_atoms;
+      h->n_atoms = na;
+      h->supp_ptr_h.assign(nl->supp_ptr, nl->supp_ptr + na + 1);
+      check(h->supp_ptr_h[0] == 0, "supp_ptr[0] must be 0");
+      for (int J = 0; J < na; ++J) check(h->supp_ptr_h[J + 1] >= h->supp_ptr_h[J], "supp_ptr must be non-decreasing");
+      const int64_t nsupp = h->supp_ptr_h[na];
+      check(nsupp < (int64_t)1 << 31, "too many support points");
+      h->supp_idx_h.assign(nl->supp_idx, nl->supp_idx + nsupp);
+      h->nproj_h.assign(nl->nproj, nl->nproj + na);
+      int64_t nchi = 0, npt = 0;
+      for (int J = 0; J < na; ++J) {
+        check(h->nproj_h[J] >= 1, "nproj must be >= 1");
+        const int64_t nj = h->supp_ptr_h[J + 1] - h->supp_ptr_h[J];
+        for (int64_t s = 0; s < nj; ++s) {
+          const int64_t i = h->supp_idx_h[h->supp_ptr_h[J] + s];
+          check(i >= 0 && i < nd, "support index outside the grid");
+          if (s > 0) check(i > h->supp_idx_h[h->supp_ptr_h[J] + s - 1], "support indices must increase");
+        }
+        nchi += nj * h->nproj_h[J];
+        npt += h->nproj_h[J];
+      }
+      check(npt < (int64_t)1 << 30 && nchi < ((int64_t)1 << 40), "too many projectors");
+      h->np_tot = (int)npt;
+      h->chi_h.assign(nl->chi, nl->chi + nchi);
+      h->gamma_h.assign(nl->gamma, nl->gamma + npt);
+      for (double v : h->chi_h) check(std::isfinite(v), "chi must be finite");
+      for (double v : h->gamma_h) check(std::isfinite(v), "gamma must be finite");
+    }
+
+    HIP_TRY(hipGetDevice(&h->device));
+    BLAS_TRY(rocblas_create_handle(&h->blas));
+    if (const char* e = std::getenv("CHEFSI_HX_PY")) h->py_override = std::atoi(e);  // tiling only
+
+    h->veff64 = upload(h->veff_h.data(), nd);
+    std::vector<float> v32(h->veff_h.begin(), h->veff_h.end());
+    h->veff32 = upload(v32.data(), nd);
+
+    if (h->np_tot > 0) {
+      const int na = h->n_atoms;
+      std::vector<int> soff(na + 1), poff(na);
+      std::vector<int64_t> coff(na);
+      int64_t c = 0;
+      int p = 0;
+      for (int J = 0; J < na; ++J) {
+        soff[J] = (int)h->supp_ptr_h[J];
+        coff[J] = c;
+        poff[J] = p;
+        c += (h->supp_ptr_h[J + 1] - h->supp_ptr_h[J]) * h->nproj_h[J];
+        p += h->nproj_h[J];
+      }
+      soff[na] = (int)h->supp_ptr_h[na];
+      std::vector<double> gdv(h->np_tot);
+      for (int q = 0; q < h->np_tot; ++q) gdv[q] = h->gamma_h[q] * h->dv;
+      // point-major scatter table: row i lists (projector column, chi value), atoms in order
+      std::vector<int> cnt(nd + 1, 0);
+      for (int J = 0; J < na; ++J)
+        for (int64_t s = h->supp_ptr_h[J]; s < h->supp_ptr_h[J + 1]; ++s) cnt[h->supp_idx_h[s] + 1] += h->nproj_h[J];
+      for (int64_t i = 0; i < nd; ++i) cnt[i + 1] += cnt[i];
+      const int64_t nent = cnt[nd];
+      check(nent < (int64_t)1 << 31, "too many projector entries");
+      std::vector<int> row(cnt), fill(cnt.begin(), cnt.end() - 1), eproj(nent);
+      std::vector<double> eval(nent);
+      for (int J = 0; J < na; ++J) {
+        const int64_t nj = h->supp_ptr_h[J + 1] - h->supp_ptr_h[J];
+        for (int64_t s = 0; s < nj; ++s) {
+          const int i = h->supp_idx_h[h->supp_ptr_h[J] + s];
+          for (int a = 0; a < h->nproj_h[J]; ++a) {
+            const int pos = fill[i]++;
+            eproj[pos] = poff[J] + a;
+            eval[pos] = h->chi_h[coff[J] + a * nj + s];
+          }
+        }
+      }
+      h->supp_off = upload(soff.data(), soff.size());
+      h->supp_idx = upload(h->supp_idx_h.data(), h->supp_idx_h.size());
+      h->chi_off = upload(coff.data(), coff.size());
+      h->nproj = upload(h->nproj_h.data(), h->nproj_h.size());
+      h->poff = upload(poff.data(), poff.size());
+      h->chi64 = upload(h->chi_h.data(), h->chi_h.size());
+      std::vector<float> chi32(h->chi_h.begin(), h->chi_h.end());
+      h->chi32 = upload(chi32.data(), chi32.size());
+      h->gdv64 = upload(gdv.data(), gdv.size());
+      std::vector<float> gdv32(gdv.begin(), gdv.end());
+      h->gdv32 = upload(gdv32.data(), gdv32.size());
+      h->nl_row = upload(row.data(), row.size());
+      h->nl_proj = upload(eproj.data(), eproj.size());
+      h->nl_val64 = upload(eval.data(), eval.size());
+      std::vector<float> eval32(eval.begin(), eval.end());
+      h->nl_val32 = upload(eval32.data(), eval32.size());
+    }
+    *out = h;
+    return CHEFSI_OK;
+  } catch (const Error& e) {
+    release(h);
+    delete h;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    release(h);
+    delete h;
+    return CHEFSI_ERR_OOM;
+  } catch (...) {
+    release(h);
+    delete h;
+    return CHEFSI_ERR_HIP;
+  }
+}
+
+void chefsi_destroy(chefsi_handle_t* h) {
+  if (!h) return;
+  release(h);
+  delete h;
+}
+
+int chefsi_workspace_bytes(const chefsi_handle_t* hc, int32_t ns, size_t* bytes) {
+  chefsi_handle* h = const_cast<chefsi_handle*>(hc);
+  return guarded(h, [&] {
+    check(bytes != nullptr, "bytes is NULL");
+    check_ns(h, ns);
+    *bytes = layout(h, ns).total;
+  });
+}
+
+int chefsi_spectral_bounds(const chefsi_handle_t* hc, double* lam_lo, double* lam_cut, double* lam_hi) {
+  chefsi_handle* h = const_cast<chefsi_handle*>(hc);
+  return guarded(h, [&] {
+    double s = std::fabs(h->w[0]);
+    for (int p = 1; p <= h->radius; ++p) s += 2.0 * std::fabs(h->w[p]);
+    double kin = 0.0;
+    for (int d = 0; d < 3; ++d) kin += 0.5 * s / (h->h[d] * h->h[d]);
+    double vmax = -INFINITY, vmin = INFINITY;
+    for (double v : h->veff_h) {
+      vmax = std::max(vmax, v);
+      vmin = std::min(vmin, v);
+    }
+    std::vector<double> row(h->nd, 0.0);
+    bool negative = false;
+    int64_t coff = 0;
+    int q = 0;
+    for (int J = 0; J < h->n_atoms; ++J) {
+      const int64_t s0 = h->supp_ptr_h[J], nj = h->supp_ptr_h[J + 1] - s0;
+      for (int a = 0; a < h->nproj_h[J]; ++a, ++q) {
+        const double* c = h->chi_h.data() + coff + a * nj;
+        double l1 = 0.0;
+        for (int64_t t = 0; t < nj; ++t) l1 += std::fabs(c[t]);
+        const double g = std::fabs(h->gamma_h[q]);
+        if (h->gamma_h[q] < 0) negative = true;
+        for (int64_t t = 0; t < nj; ++t) row[h->supp_idx_h[s0 + t]] += g * std::fabs(c[t]) * l1 * h->dv;
+      }
+      coff += nj * h->nproj_h[J];
+    }
+    double nlb = 0.0;
+    for (double v : row) nlb = std::max(nlb, v);
+    const double hi = kin + vmax + nlb;
+    const double lo = vmin - (negative ? nlb : 0.0);
+    if (lam_hi) *lam_hi = hi;
+    if (lam_lo) *lam_lo = lo;
+    if (lam_cut) *lam_cut = lo + 0.1 * (hi - lo);
+  });
+}
+
+int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns, void* ws, size_t ws_bytes, void* stream) {
+  return guarded(h, [&] {
+    check(X != nullptr && Y != nullptr && X != Y, "X and Y must be distinct device blocks");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      apply_fused<double, double, double>(h, (const double*)X, nullptr, (double*)Y, ns, 1.0, 0.0, 0.0,
+                                          at<double>(ws, L.alpha), s);
+    else
+      apply_fused<float, float, float>(h, (const float*)X, nullptr, (float*)Y, ns, 1.0, 0.0, 0.0,
+                                       at<float>(ws, L.alpha), s);
+  });
+}
+
+int chefsi_filter(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
+                  double lam_hi, void* ws, size_t ws_bytes, void* stream) {
+  return guarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check(degree >= 1, "degree must be >= 1");
+    check_ns(h, ns);
+    check_bounds(lam_lo, lam_cut, lam_hi);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64) {
+      double* A = (double*)X;
+      double* r = run_filter<double>(h, A, at<double>(ws, L.bufB), ns, degree, lam_lo, lam_cut, lam_hi,
+                                     at<double>(ws, L.alpha), s);
+      if (r != A) copy_block<double>(h, A, r, ns, s);
+    } else {
+      float* A = (float*)X;
+      float* r = run_filter<float>(h, A, at<float>(ws, L.bufB), ns, degree, lam_lo, lam_cut, lam_hi,
+                                   at<float>(ws, L.alpha), s);
+      if (r != A) copy_block<float>(h, A, r, ns, s);
+    }
+  });
+}
+
+int chefsi_project(chefsi_handle_t* h, const void* X, int32_t ns, double* Hs, double* Ms, void* ws,
+                   size_t ws_bytes, void* stream) {
+  return guarded(h, [&] {
+    check(X != nullptr && Hs != nullptr && Ms != nullptr, "null pointer");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64) {
+      double* Y = at<double>(ws, L.bufB);
+      apply_fused<double, double, double>(h, (const double*)X, nullptr, Y, ns, 1.0, 0.0, 0.0,
+                                          at<double>(ws, L.alpha), s);
+      gram_pair<double, double>(h, (const double*)X, Y, ns, L, ws, Hs, Ms, s);
+    } else {
+      float* Y = at<float>(ws, L.bufB);
+      apply_fused<float, float, float>(h, (const float*)X, nullptr, Y, ns, 1.0, 0.0, 0.0, at<float>(ws, L.alpha),
+                                       s);
+      gram_pair<float, float>(h, (const float*)X, Y, ns, L, ws, Hs, Ms, s);
+    }
+  });
+}
+
+int chefsi_eigh(chefsi_handle_t* h, double* Hs, double* Ms, double* D, int32_t ns, void* ws, size_t ws_bytes,
+                void* stream) {
+  return guarded(h, [&] {
+    check(Hs != nullptr && Ms != nullptr && D != nullptr, "null pointer");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    dense_eig(h, Hs, Ms, D, ns, L, ws, s);
+    check_info(h, ws, L, ns, s);
+  });
+}
+
+int chefsi_rotate(chefsi_handle_t* h, void* X, const double* Z, int32_t ns, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return guarded(h, [&] {
+    check(X != nullptr && Z != nullptr, "null pointer");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64) {
+      double* B = at<double>(ws, L.bufB);
+      rotate_into<double>(h, (const double*)X, Z, B, ns, s);
+      copy_block<double>(h, (double*)X, B, ns, s);
+    } else {
+      float* B = at<float>(ws, L.bufB);
+      rotate_into<float>(h, (const float*)X, Z, B, ns, s);
+      copy_block<float>(h, (float*)X, B, ns, s);
+    }
+  });
+}
+
+int chefsi_step(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
+                double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host) {
+  return guarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check(degree >= 1, "degree must be >= 1");
+    check_ns(h, ns);
+    check_bounds(lam_lo, lam_cut, lam_hi);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      step_impl<double>(h, (double*)X, ns, degree, lam_lo, lam_cut, lam_hi, ws, L, s, ritz_host);
+    else
+      step_impl<float>(h, (float*)X, ns, degree, lam_lo, lam_cut, lam_hi, ws, L, s, ritz_host);
+  });
+}
+
+int chefsi_solve(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, int32_t n_iter, double lam_lo,
+                 double lam_cut, double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host,
+                 double* lam_lo_out, double* lam_cut_out) {
+  return guarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check(degree >= 1 && n_iter >= 1, "degree and n_iter must be >= 1");
+    check_ns(h, ns);
+    check_bounds(lam_lo, lam_cut, lam_hi);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> d(ns);
+    double lo = lam_lo, cut = lam_cut;
+    for (int it = 0; it < n_iter; ++it) {
+      check_bounds(lo, cut, lam_hi);
+      if (h->precision == CHEFSI_FP64)
+        step_impl<double>(h, (double*)X, ns, degree, lo, cut, lam_hi, ws, L, s, d.data());
+      else
+        step_impl<float>(h, (float*)X, ns, degree, lo, cut, lam_hi, ws, L, s, d.data());
+      lo = d[0];
+      cut = d[ns - 1];
+    }
+    if (ritz_host) std::memcpy(ritz_host, d.data(), (size_t)ns * 8);
+    if (lam_lo_out) *lam_lo_out = lo;
+    if (lam_cut_out) *lam_cut_out = cut;
+  });
+}
+
+int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
+                       double* ritz_host) {
+  return guarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      refine_impl<double>(h, (double*)X, ns, ws, L, s, ritz_host);
+    else
+      refine_impl<float>(h, (float*)X, ns, ws, L, s, ritz_host);
+  });
+}
+
+int chefsi_profile_enable(chefsi_handle_t* h, int32_t on) {
+  return guarded(h, [&] { h->prof_on = on != 0; });
+}
+
+int chefsi_profile_reset(chefsi_handle_t* h) {
+  return guarded(h, [&] {
+    prof_collect(h);
+    for (int i = 0; i < kNumProf; ++i) {
+      h->prof_ms[i] = 0.0;
+      h->prof_n[i] = 0;
+    }
+  });
+}
+
+int chefsi_profile_read(chefsi_handle_t* h, int32_t kernel_id, double* total_ms, int64_t* launches) {
+  return guarded(h, [&] {
+    check(kernel_id >= 0 && kernel_id < kNumProf, "kernel_id out of range");
+    prof_collect(h);
+    if (total_ms) *total_ms = h->prof_ms[kernel_id];
+    if (launches) *launches = h->prof_n[kernel_id];
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libchefsi.
+// Not part of the public ABI (that is include/chefsi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace chefsi {
+
+constexpr int kMaxRadius = 6;  // finite-difference order up to 12
+constexpr int kHxMaxThreads = 512;  // stencil block size cap (keeps 256 VGPRs per lane)
+constexpr int kHxMaxHalo = 4;       // halo values each stencil thread stages per plane
+
+// ---------------------------------------------------------------------------
+// hx_apply: fused  out = sa * ((H x) - sc * x) + sb * prev   for a block of vectors.
+// H x = c0 x + sum_p cx[p](x[i+-p ex]) + cy.. + cz.. + veff x + sum_e val[e] alpha[proj[e]].
+// TI: element type of x; TC: arithmetic type; TO: element type of prev/out.
+// ---------------------------------------------------------------------------
+template <typename TI, typename TC, typename TO>
+struct HxArgs {
+  const TI* x;
+  const TO* prev;  // may be null when sb == 0
+  TO* out;
+  const TC* veff;
+  // point-major nonlocal scatter table (may be null when there are no projectors)
+  const int* nl_row;   // nd + 1
+  const int* nl_proj;  // entries: projector column in alpha
+  const TC* nl_val;    // entries: chi value at the point
+  const TC* alpha;     // ns x np_tot, projector index fastest
+  int np_tot;
+  int nx, ny, nz;
+  int64_t nd;          // leading dimension of x, prev, out
+  int per_x, per_y, per_z;  // 1 = periodic, 0 = Dirichlet
+  TC c0;                    // centre weight: -1/2 w0 sum_d h_d^-2
+  TC cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];  // -1/2 w_p / h_d^2
+  TC sa, sc, sb;
+  // tiling
+  int nyg;   // thread rows (y groups) per block; threads used = nx * nyg
+  int ty;    // tile rows = nyg * PY
+  int nty;   // tiles along y
+  int zc;    // planes per z chunk
+};
+
+struct HxPlan {
+  bool ok = false;  // false: no tiling fits this grid
+  int py = 2;
+  int nyg = 1;
+  int ty = 2;
+  int nty = 1;
+  int zc = 1;
+  int nzc = 1;
+  int threads = 64;
+  size_t lds_bytes = 0;
+};
+
+// Choose the tiling for one grid (deterministic in the shape only).
+HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override);
+
+template <typename TI, typename TC, typename TO>
+hipError_t launch_hx(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int radius, int ns, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// nl_project: alpha[v * np_tot + q] = gdv[q] * sum_{s in S_J} chi_J[s, a] * y[v * nd + S_J[s]]
+// for every atom J, projector a (q = poff[J] + a) and vector v.
+// ---------------------------------------------------------------------------
+template <typename TI, typename TC>
+struct NlArgs {
+  const TI* y;
+  int64_t nd;
+  int ns;
+  int n_atoms;
+  const int* supp_off;  // n_atoms + 1, offsets into supp_idx
+  const int* supp_idx;
+  const int64_t* chi_off;  // n_atoms, offset of chi_J
+  const int* nproj;        // n_atoms
+  const int* poff;         // n_atoms, first projector column of atom J
+  const TC* chi;
+  const TC* gdv;           // gamma * dV per projector column
+  TC* alpha;
+  int np_tot;
+};
+
+template <typename TI, typename TC>
+hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Dense products on MFMA.
+// gram:   partial[split][tile] = A(:, I)^T B(:, J) over a K range, for upper tiles I <= J.
+// reduce: C(i, j) = C(j, i) = sum_split partial (i <= j), C is ns x ns, ld ns, FP64.
+// rotate: O = X Z  (X: nd x ns, ld nd; Z: ns x ns, ld ns; O: nd x ns, ld nd).
+// ---------------------------------------------------------------------------
+struct GramPlan {
+  int tile = 128;
+  int nt = 1;        // tiles per dimension
+  int ntiles = 1;    // upper tiles nt (nt + 1) / 2
+  int splits = 1;
+  int64_t kchunk = 0;
+  size_t partial_bytes = 0;
+};
+
+GramPlan plan_gram(int64_t nd, int ns);
+
+template <typename TA, typename TB>
+hipError_t launch_gram_f64(const TA* A, const TB* B, int64_t nd, int ns, const GramPlan& p, double* partial,
+                           hipStream_t s);
+
+hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, double* C, hipStream_t s);
+
+template <typename TX, typename TO>
+hipError_t launch_rotate_f64(const TX* X, const double* Z, TO* O, int64_t nd, int ns, hipStream_t s);
+
+}  // namespace chefsi
