@@ -105,10 +105,13 @@ struct chefsi_handle {
   float* chi32 = nullptr;
   double* gdv64 = nullptr;
   float* gdv32 = nullptr;
-  int* nl_row = nullptr;
-  int* nl_proj = nullptr;
-  double* nl_val64 = nullptr;
-  float* nl_val32 = nullptr;
+  // projector entries grouped by (y tile, z plane) of the stencil tiling: one record per touched point
+  HxPlan hx_plan;  // tiling for ns = 1 (only the z chunking depends on ns)
+  int* rec_ptr = nullptr;
+  int4* rec = nullptr;
+  int* ent_col = nullptr;
+  double* ent_val64 = nullptr;
+  float* ent_val32 = nullptr;
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -134,16 +137,39 @@ struct WsLayout {
 
 size_t elem_bytes(const chefsi_handle* h) { return h->precision == CHEFSI_FP64 ? 8 : 4; }
 
+// Device workspace of the FP64 dense stage (Cholesky, two triangular solves for the
+// reduced matrix, symmetric eigensolve, back substitution); the calls run in sequence,
+// so the largest single request is enough.
 size_t solver_workspace(chefsi_handle* h, int ns) {
   auto it = h->solver_ws_cache.find(ns);
   if (it != h->solver_ws_cache.end()) return it->second;
-  size_t sz = 0;
-  BLAS_TRY(rocblas_start_device_memory_size_query(h->blas));
-  rocsolver_dsygvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr,
-                   ns, nullptr, nullptr, nullptr);
-  BLAS_TRY(rocblas_stop_device_memory_size_query(h->blas, &sz));
-  h->solver_ws_cache[ns] = sz;
-  return sz;
+  const double one = 1.0;
+  size_t best = 0, sz = 0;
+  auto query = [&](auto&& call) {
+    BLAS_TRY(rocblas_start_device_memory_size_query(h->blas));
+    call();
+    BLAS_TRY(rocblas_stop_device_memory_size_query(h->blas, &sz));
+    best = std::max(best, sz);
+  };
+  query([&] { rocsolver_dpotrf(h->blas, rocblas_fill_upper, ns, nullptr, ns, nullptr); });
+  query([&] {
+    rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                  rocblas_diagonal_non_unit, ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocblas_dtrsm(h->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                  rocblas_diagonal_non_unit, ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                  rocblas_diagonal_non_unit, ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocsolver_dsyevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr,
+                     nullptr);
+  });
+  h->solver_ws_cache[ns] = best;
+  return best;
 }
 
 WsLayout layout(chefsi_handle* h, int ns) {
@@ -258,9 +284,10 @@ HxArgs<TI, TC, TO> hx_args(const chefsi_handle* h, const TI* x, const TO* prev, 
   a.prev = prev;
   a.out = out;
   a.veff = veff;
-  a.nl_row = h->np_tot > 0 ? h->nl_row : nullptr;
-  a.nl_proj = h->nl_proj;
-  a.nl_val = nl_val;
+  a.rec_ptr = h->np_tot > 0 ? h->rec_ptr : nullptr;
+  a.rec = h->rec;
+  a.ent_col = h->ent_col;
+  a.ent_val = nl_val;
   a.alpha = alpha;
   a.np_tot = h->np_tot;
   a.nx = h->n[0];
@@ -314,12 +341,12 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
   const TC* gdv;
   if constexpr (sizeof(TC) == 8) {
     veff = h->veff64;
-    nlv = h->nl_val64;
+    nlv = h->ent_val64;
     chi = h->chi64;
     gdv = h->gdv64;
   } else {
     veff = h->veff32;
-    nlv = h->nl_val32;
+    nlv = h->ent_val32;
     chi = h->chi32;
     gdv = h->gdv32;
   }
@@ -333,10 +360,7 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
   a.sc = TC(sc);
   a.sb = TC(sb);
   const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->py_override);
-  a.nyg = p.nyg;
-  a.ty = p.ty;
-  a.nty = p.nty;
-  a.zc = p.zc;
+  if (!p.ok || p.ty != h->hx_plan.ty) throw Error{CHEFSI_ERR_HIP, "stencil tiling differs from the one the projector records were built for"};
   ProfScope ps(h, P_HX, s);
   HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
   ps.done();
@@ -391,31 +415,48 @@ void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayou
   }
 }
 
-// Hs Z = Ms Z D in FP64 on the device (rocSOLVER dsygvd: Cholesky, reduction, divide and conquer).
+// Hs Z = Ms Z D in FP64 on the device (Alg. 1, Diagonalization; Sec. 2.3), as the standard
+// reduction of a symmetric-definite pencil: Ms = U^T U (Cholesky), C = U^-T Hs U^-1,
+// C = W D W^T (divide and conquer), Z = U^-1 W.  Z overwrites Hs, U overwrites Ms.
+// info[0] receives the Cholesky status, info[1] the eigensolver status.
 void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
                hipStream_t s) {
   ProfScope ps(h, P_EIG, s);
+  const double one = 1.0;
   BLAS_TRY(rocblas_set_stream(h->blas, s));
   BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
   rocblas_int* info = at<rocblas_int>(ws, L.info);
-  BLAS_TRY(rocsolver_dsygvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, Hs, ns, Ms, ns,
-                            D, at<double>(ws, L.e), info));
+  BLAS_TRY(rocsolver_dpotrf(h->blas, rocblas_fill_upper, ns, Ms, ns, info));
+  BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                         rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
+  BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
+  BLAS_TRY(rocsolver_dsyevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, Hs, ns, D,
+                            at<double>(ws, L.e), info + 1));
+  BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                         rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
   ps.done();
 }
 
-void check_info(chefsi_handle* h, void* ws, const WsLayout& L, int ns, hipStream_t s) {
-  rocblas_int info = 0;
-  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (info > ns) {
-    h->last_info = info;
+// Map the two dense-stage status words to a status (the Cholesky failure is reported as
+// ns + order of the failing leading minor, the convention of the LAPACK generalized solvers).
+void raise_info(chefsi_handle* h, const rocblas_int* info, int ns) {
+  if (info[0] > 0) {
+    h->last_info = ns + info[0];
     throw Error{CHEFSI_ERR_NOT_POSDEF, "Cholesky of the overlap matrix failed (leading minor " +
-                                           std::to_string(info - ns) + ")"};
+                                           std::to_string(info[0]) + ")"};
   }
-  if (info > 0) {
-    h->last_info = info;
+  if (info[1] > 0) {
+    h->last_info = info[1];
     throw Error{CHEFSI_ERR_EIG, "dense eigensolver did not converge"};
   }
+}
+
+void check_info(chefsi_handle* h, void* ws, const WsLayout& L, int ns, hipStream_t s) {
+  rocblas_int info[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  raise_info(h, info, ns);
 }
 
 template <typename T>
@@ -434,19 +475,12 @@ void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hi
 
 void ritz_to_host(chefsi_handle* h, const double* D, int ns, double* ritz_host, void* ws, const WsLayout& L,
                   hipStream_t s) {
-  rocblas_int info = 0;
+  rocblas_int info[2] = {0, 0};
   std::vector<double> d(ns);
   HIP_TRY(hipMemcpyAsync(d.data(), D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (info > ns) {
-    h->last_info = info;
-    throw Error{CHEFSI_ERR_NOT_POSDEF, "Cholesky of the overlap matrix failed"};
-  }
-  if (info > 0) {
-    h->last_info = info;
-    throw Error{CHEFSI_ERR_EIG, "dense eigensolver did not converge"};
-  }
+  raise_info(h, info, ns);
   for (int i = 0; i < ns; ++i)
     if (!std::isfinite(d[i])) throw Error{CHEFSI_ERR_NONFINITE, "non-finite Ritz value"};
   if (ritz_host) std::memcpy(ritz_host, d.data(), (size_t)ns * 8);
@@ -529,8 +563,9 @@ T* upload(const T* src, size_t n) {
 
 void release(chefsi_handle* h) {
   void* ptrs[] = {h->veff64, h->veff32, h->supp_off, h->supp_idx, h->chi_off,  h->nproj,    h->poff,
-                  h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->nl_row,   h->nl_proj,  h->nl_val64,
-                  h->nl_val32};
+                  h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->rec_ptr,  h->rec,      h->ent_col,
+                  h->ent_val64,
+                  h->ent_val32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& p : h->ev_pending) {
@@ -642,6 +677,8 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     HIP_TRY(hipGetDevice(&h->device));
     BLAS_TRY(rocblas_create_handle(&h->blas));
     if (const char* e = std::getenv("CHEFSI_HX_PY")) h->py_override = std::atoi(e);  // tiling only
+    h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->py_override);
+    check(h->hx_plan.ok, "no stencil tiling fits this grid");
 
     h->veff64 = upload(h->veff_h.data(), nd);
     std::vector<float> v32(h->veff_h.begin(), h->veff_h.end());
@@ -663,14 +700,14 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       soff[na] = (int)h->supp_ptr_h[na];
       std::vector<double> gdv(h->np_tot);
       for (int q = 0; q < h->np_tot; ++q) gdv[q] = h->gamma_h[q] * h->dv;
-      // point-major scatter table: row i lists (projector column, chi value), atoms in order
+      // point-major table: point i lists (projector column, chi value), atoms in order
       std::vector<int> cnt(nd + 1, 0);
       for (int J = 0; J < na; ++J)
         for (int64_t s = h->supp_ptr_h[J]; s < h->supp_ptr_h[J + 1]; ++s) cnt[h->supp_idx_h[s] + 1] += h->nproj_h[J];
       for (int64_t i = 0; i < nd; ++i) cnt[i + 1] += cnt[i];
       const int64_t nent = cnt[nd];
       check(nent < (int64_t)1 << 31, "too many projector entries");
-      std::vector<int> row(cnt), fill(cnt.begin(), cnt.end() - 1), eproj(nent);
+      std::vector<int> fill(cnt.begin(), cnt.end() - 1), eproj(nent);
       std::vector<double> eval(nent);
       for (int J = 0; J < na; ++J) {
         const int64_t nj = h->supp_ptr_h[J + 1] - h->supp_ptr_h[J];
@@ -683,6 +720,43 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
           }
         }
       }
+      // regroup by (y tile, z plane) of the stencil tiling: one record per touched point,
+      // its entries contiguous and in atom order
+      const HxPlan& hp = h->hx_plan;
+      const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+      const int64_t nkeys = (int64_t)hp.nty * nz;
+      std::vector<int> rptr(nkeys + 1, 0);
+      auto key_of = [&](int64_t i) {
+        const int y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        return (int64_t)(y / hp.ty) * nz + z;
+      };
+      for (int64_t i = 0; i < nd; ++i)
+        if (cnt[i + 1] > cnt[i]) rptr[key_of(i) + 1] += 1;
+      for (int64_t k = 0; k < nkeys; ++k) rptr[k + 1] += rptr[k];
+      const int nrec = rptr[nkeys];
+      std::vector<int> rfill(rptr.begin(), rptr.end() - 1);
+      std::vector<int> rec_pt(nrec);
+      for (int64_t i = 0; i < nd; ++i)
+        if (cnt[i + 1] > cnt[i]) rec_pt[rfill[key_of(i)]++] = (int)i;
+      std::vector<int4> recs(std::max(nrec, 1), make_int4(0, 0, 0, 0));
+      std::vector<int> ecol(std::max<int64_t>(nent, 1), 0);
+      std::vector<double> evals(std::max<int64_t>(nent, 1), 0.0);
+      int64_t e = 0;
+      for (int r = 0; r < nrec; ++r) {
+        const int64_t i = rec_pt[r];
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny);
+        recs[r] = make_int4((y % hp.ty) * nx + x, (int)e, cnt[i + 1] - cnt[i], 0);
+        for (int k = cnt[i]; k < cnt[i + 1]; ++k, ++e) {
+          ecol[e] = eproj[k];
+          evals[e] = eval[k];
+        }
+      }
+      h->rec_ptr = upload(rptr.data(), rptr.size());
+      h->rec = upload(recs.data(), recs.size());
+      h->ent_col = upload(ecol.data(), ecol.size());
+      h->ent_val64 = upload(evals.data(), evals.size());
+      std::vector<float> ev32(evals.begin(), evals.end());
+      h->ent_val32 = upload(ev32.data(), ev32.size());
       h->supp_off = upload(soff.data(), soff.size());
       h->supp_idx = upload(h->supp_idx_h.data(), h->supp_idx_h.size());
       h->chi_off = upload(coff.data(), coff.size());
@@ -694,11 +768,6 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       h->gdv64 = upload(gdv.data(), gdv.size());
       std::vector<float> gdv32(gdv.begin(), gdv.end());
       h->gdv32 = upload(gdv32.data(), gdv32.size());
-      h->nl_row = upload(row.data(), row.size());
-      h->nl_proj = upload(eproj.data(), eproj.size());
-      h->nl_val64 = upload(eval.data(), eval.size());
-      std::vector<float> eval32(eval.begin(), eval.end());
-      h->nl_val32 = upload(eval32.data(), eval32.size());
     }
     *out = h;
     return CHEFSI_OK;

@@ -10,12 +10,15 @@
 namespace chefsi {
 
 constexpr int kMaxRadius = 6;  // finite-difference order up to 12
-constexpr int kHxMaxThreads = 512;  // stencil block size cap (keeps 256 VGPRs per lane)
+constexpr int kHxMaxThreads = 512;  // stencil threads per block (keeps 256 VGPRs per lane)
 constexpr int kHxMaxHalo = 4;       // halo values each stencil thread stages per plane
 
 // ---------------------------------------------------------------------------
 // hx_apply: fused  out = sa * ((H x) - sc * x) + sb * prev   for a block of vectors.
-// H x = c0 x + sum_p cx[p](x[i+-p ex]) + cy.. + cz.. + veff x + sum_e val[e] alpha[proj[e]].
+// H x = c0 x + sum_p cx[p](x[i+-p ex]) + cy.. + cz.. + veff x + (projector term).
+// The projector term at a point is sum over its entries of chi * alpha[v][column]; the
+// entries are grouped into per-(y tile, z plane) point records so that a block can
+// gather them for a whole plane ahead of time.
 // TI: element type of x; TC: arithmetic type; TO: element type of prev/out.
 // ---------------------------------------------------------------------------
 template <typename TI, typename TC, typename TO>
@@ -24,14 +27,16 @@ struct HxArgs {
   const TO* prev;  // may be null when sb == 0
   TO* out;
   const TC* veff;
-  // point-major nonlocal scatter table (may be null when there are no projectors)
-  const int* nl_row;   // nd + 1
-  const int* nl_proj;  // entries: projector column in alpha
-  const TC* nl_val;    // entries: chi value at the point
-  const TC* alpha;     // ns x np_tot, projector index fastest
+  // projector records (rec_ptr == null when there are no projectors)
+  const int* rec_ptr;   // nty * nz + 1: records of (tile t, plane z) are [rec_ptr[t*nz+z], rec_ptr[t*nz+z+1])
+  const int4* rec;      // {local point index ly*nx+x, first entry, entry count, 0}
+  const int* ent_col;   // alpha column of each entry
+  const TC* ent_val;    // chi value of each entry
+  const TC* alpha;      // ns x np_tot, projector column fastest
   int np_tot;
+  int alpha_lds;        // 1: stage the block's alpha row in LDS
   int nx, ny, nz;
-  int64_t nd;          // leading dimension of x, prev, out
+  int64_t nd;           // leading dimension of x, prev, out
   int per_x, per_y, per_z;  // 1 = periodic, 0 = Dirichlet
   TC c0;                    // centre weight: -1/2 w0 sum_d h_d^-2
   TC cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];  // -1/2 w_p / h_d^2
@@ -41,6 +46,9 @@ struct HxArgs {
   int ty;    // tile rows = nyg * PY
   int nty;   // tiles along y
   int zc;    // planes per z chunk
+  int nzc;   // z chunks
+  int64_t nblocks;  // nty * nzc * ns
+  int per_xcd;      // blocks per XCD after padding the grid to a multiple of 8
 };
 
 struct HxPlan {
@@ -52,10 +60,11 @@ struct HxPlan {
   int zc = 1;
   int nzc = 1;
   int threads = 64;
-  size_t lds_bytes = 0;
+  int kh = 4;        // halo values each thread stages per plane (2 or 4)
+  size_t lds_tile_bytes = 0;  // two tile planes
 };
 
-// Choose the tiling for one grid (deterministic in the shape only).
+// Choose the tiling for one grid (deterministic in the shape only; ns only sets the z chunks).
 HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override);
 
 template <typename TI, typename TC, typename TO>

@@ -8,24 +8,34 @@
 //
 //   out[i] = sa * ((H y)[i] - sc * y[i]) + sb * prev[i]
 //
-// Mapping on gfx950 (wave64, 160 KB LDS per CU):
+// Mapping on gfx950 (wave64, 160 KB LDS per CU, 8 XCDs with private L2):
 //   * one block = one orbital x one tile of whole x-rows (nx wide, ty = nyg*PY
 //     rows) x one chunk of z-planes; a thread owns PY consecutive y rows at one x;
+//   * blocks are dealt to XCDs so that all tiles of one orbital and z chunk run on
+//     the same XCD at about the same time: their halo rows hit the same L2;
 //   * the block marches through z.  Each thread keeps its 2r+1 z-neighbours in a
-//     register queue (the z part of the stencil never touches LDS) and prefetches
-//     the next plane one iteration ahead;
-//   * the current plane of the tile plus r halo rows above and below sits in LDS;
-//     x neighbours wrap inside the row (periodic) or read as zero (Dirichlet), so
-//     whole-row tiles need no x halo at all; y neighbours are read once per
-//     column and reused by the PY rows the thread owns;
-//   * the projector term is gathered from a point-major table (no atomics, fixed
-//     summation order, so results are bitwise reproducible).
+//     register queue (the z part never touches LDS) and fetches the next plane one
+//     iteration ahead.  The current plane of the tile plus r halo rows above and
+//     below sits in LDS, double-buffered so one barrier per plane suffices; x
+//     neighbours wrap inside the row (periodic) or read as zero (Dirichlet), so whole
+//     rows need no x halo; y neighbours are read once per column and reused by the
+//     PY rows a thread owns.  The kernel is kept lean in registers: on this path
+//     occupancy hides memory latency better than deeper per-thread prefetch;
+//   * global reads are buffer loads: a Dirichlet ghost is an out-of-range offset,
+//     which returns zero without touching memory, so the loads need no branches;
+//   * projector term (NL): the block stages its orbital's gather coefficients alpha
+//     in LDS; the points of each tile plane that projectors touch are listed as
+//     records whose entries are fetched a plane ahead and summed into an LDS
+//     accumulator by one thread each (fixed order, no atomics: bitwise reproducible).
 #include "common.h"
 
 #include <algorithm>
 #include <cstdlib>
 
 namespace chefsi {
+
+constexpr unsigned kOOB = 0x80000000u;  // any buffer offset at or past the end reads as zero
+constexpr int kPrefEnt = 4;             // entries of a projector record fetched a plane ahead
 
 __device__ __forceinline__ int wrap_index(int v, int n) {
   v %= n;
@@ -44,123 +54,207 @@ __device__ __forceinline__ int plane_offset(int pz, int nplane, int nz, int per_
   return (pz < 0 || pz >= nz) ? -1 : nplane * pz;
 }
 
-template <typename TI>
-__device__ __forceinline__ TI load_at(const TI* __restrict__ xv, int roff, int poff) {
-  return (roff < 0 || poff < 0) ? TI(0) : xv[roff + poff];
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <typename TI, typename TC, typename TO, int R, int PY>
+// element offsets -> byte offset, or out of range when either part is invalid (< 0)
+template <typename T>
+__device__ __forceinline__ unsigned boff(int a, int b) {
+  return (a < 0 || b < 0) ? kOOB : (unsigned)(a + b) * (unsigned)sizeof(T);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
 __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  TI* lds = reinterpret_cast<TI*>(lds_raw);
-
   constexpr int Q = 2 * R + 1;
-  constexpr int kMaxHalo = kHxMaxHalo;  // halo values per thread (planner keeps 2R*nx <= kMaxHalo*blockDim)
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const int used = nx * a.nyg;
-  const bool active = tid < used;
-  const int x = active ? tid % nx : 0;
-  const int yg = active ? tid / nx : 0;
-  const int tile = blockIdx.x % a.nty;
-  const int zchunk = blockIdx.x / a.nty;
-  const int64_t vec = blockIdx.y;
+
+  // hardware deals consecutive block ids to the 8 XCDs in turn
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+  if (logical >= a.nblocks) return;
+  const int per_vec = a.nty * a.nzc;
+  const int64_t vec = logical / per_vec;
+  const int rem = (int)(logical % per_vec);
+  const int tile = rem % a.nty;
+  const int zchunk = rem / a.nty;
   const int y0 = tile * a.ty;
   const int z0 = zchunk * a.zc;
   const int z1 = min(z0 + a.zc, nz);
   if (z0 >= nz) return;
+  const int nzl = z1 - z0;
 
-  const TI* __restrict__ xv = a.x + vec * a.nd;
-  const int ly0 = yg * PY;  // first local row of this thread
+  const int plane_pts = a.ty * nx;
+  const int tile_elems = (a.ty + 2 * R) * nx;
+  // LDS: [record offsets of this chunk][alpha row][accumulator x2] (NL only) [tile plane x2]
+  int* s_rp = reinterpret_cast<int*>(lds_raw);
+  const int rp_slots = NL ? ((nzl + 1 + 3) & ~3) : 0;
+  TC* s_alpha = reinterpret_cast<TC*>(s_rp + rp_slots);
+  const int al_slots = (NL && a.alpha_lds) ? ((a.np_tot + 1) & ~1) : 0;
+  TC* s_nl = s_alpha + al_slots;
+  TI* s_tile = reinterpret_cast<TI*>(s_nl + (NL ? 2 * plane_pts : 0));
 
+  const TC* g_alpha = NL ? a.alpha + vec * a.np_tot : nullptr;
+  if (NL) {
+    for (int i = tid; i <= nzl; i += nthr) s_rp[i] = a.rec_ptr[tile * nz + z0 + i];
+    if (a.alpha_lds)
+      for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
+    for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
+  }
+  const TC* alpha_src = a.alpha_lds ? s_alpha : g_alpha;
+
+  const bool active = tid < nx * a.nyg;
+  const int x = active ? tid % nx : 0;
+  const int ly0 = active ? (tid / nx) * PY : 0;
   const int nplane = nx * ny;
-  int roff[PY];
-#pragma unroll
-  for (int j = 0; j < PY; ++j) roff[j] = active ? row_offset(x, y0 + ly0 + j, nx, ny, a.per_y) : -1;
+  const bool has_prev = a.prev != nullptr;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x + vec * a.nd, a.nd * (int64_t)sizeof(TI));
+  const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.veff, a.nd * (int64_t)sizeof(TC));
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(has_prev ? (const void*)(a.prev + vec * a.nd) : (const void*)a.out,
+                                              has_prev ? a.nd * (int64_t)sizeof(TO) : 0);
+  TO* ov = a.out + vec * a.nd;
 
-  // register queue: q[s][j] = value at plane (z - R + s), row y0 + ly0 + j
-  TI q[Q][PY];
-  TI pf[PY];
+  int roff[PY];  // offset of the thread's rows inside a plane, -1 for a zero row
+  bool valid[PY];
+#pragma unroll
+  for (int j = 0; j < PY; ++j) {
+    const int gy = y0 + ly0 + j;
+    roff[j] = active ? row_offset(x, gy, nx, ny, a.per_y) : -1;
+    valid[j] = active && gy < ny;
+  }
+  int hoff[KH], hdst[KH];  // halo rows: local rows [0, R) and [R + ty, ty + 2R)
+  {
+    const int nhalo = 2 * R * nx;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int e = tid + k * nthr;
+      hoff[k] = -1;
+      hdst[k] = -1;
+      if (e < nhalo) {
+        const int hr = e / nx, hxx = e % nx;
+        const int yy = hr < R ? hr : hr + a.ty;
+        hoff[k] = row_offset(hxx, y0 - R + yy, nx, ny, a.per_y);
+        hdst[k] = yy * nx + hxx;
+      }
+    }
+  }
+
+  // q[s][j] = plane (z - R + s); pf = plane z + R (fetched one plane ahead); hp = halo of plane z
+  TI q[Q][PY], pf[PY], hp[KH];
 #pragma unroll
   for (int j = 0; j < PY; ++j) q[0][j] = TI(0);
 #pragma unroll
   for (int s = 1; s < Q; ++s) {
     const int po = plane_offset(z0 - R - 1 + s, nplane, nz, a.per_z);
 #pragma unroll
-    for (int j = 0; j < PY; ++j) q[s][j] = load_at(xv, roff[j], po);
+    for (int j = 0; j < PY; ++j) q[s][j] = bload<TI>(rx, boff<TI>(roff[j], po));
   }
   {
     const int po = plane_offset(z0 + R, nplane, nz, a.per_z);
 #pragma unroll
-    for (int j = 0; j < PY; ++j) pf[j] = load_at(xv, roff[j], po);
-  }
-
-  // halo rows: local LDS rows [0, R) and [R + ty, ty + 2R), i.e. global rows y0 - R + yy
-  const int nhalo = 2 * R * nx;
-  const int kh = (nhalo + nthr - 1) / nthr;
-  TI hpf[kMaxHalo];
-  int hoff[kMaxHalo];   // source offset inside a plane (-1: zero row or unused slot)
-  int hdst[kMaxHalo];   // destination in LDS
-  {
-    const int po = plane_offset(z0, nplane, nz, a.per_z);
+    for (int j = 0; j < PY; ++j) pf[j] = bload<TI>(rx, boff<TI>(roff[j], po));
+    const int ph = plane_offset(z0, nplane, nz, a.per_z);
 #pragma unroll
-    for (int k = 0; k < kMaxHalo; ++k) {
-      const int e = tid + k * nthr;
-      hoff[k] = -1;
-      hdst[k] = -1;
-      if (k < kh && e < nhalo) {
-        const int hr = e / nx, hxx = e % nx;
-        const int yy = hr < R ? hr : hr + a.ty;
-        hoff[k] = row_offset(hxx, y0 - R + yy, nx, ny, a.per_y);
-        hdst[k] = yy * nx + hxx;
-      }
-      hpf[k] = load_at(xv, hoff[k], po);
-    }
+    for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], ph));
   }
 
-  const int row_stride = nx;
-  for (int z = z0; z < z1; ++z) {
-    // advance the queue; the plane z + R arrived in pf during the previous iteration
+  // projector records: rc is this thread's first record of the plane being prepared,
+  // rn the one of the plane after it (loaded a full iteration before it is needed)
+  int4 rc = make_int4(0, 0, 0, 0), rn = make_int4(0, 0, 0, 0);
+  int ecol[kPrefEnt];
+  TC eval[kPrefEnt];
+  auto load_record = [&](int zl) -> int4 {
+    if (zl >= nzl) return make_int4(0, 0, 0, 0);
+    const int r = s_rp[zl] + tid;
+    return r < s_rp[zl + 1] ? a.rec[r] : make_int4(0, 0, 0, 0);
+  };
+  auto load_entries = [&](const int4& r) {
+#pragma unroll
+    for (int k = 0; k < kPrefEnt; ++k) {
+      const bool ok = k < r.z;
+      ecol[k] = ok ? a.ent_col[r.y + k] : 0;
+      eval[k] = ok ? a.ent_val[r.y + k] : TC(0);
+    }
+  };
+  // sum the projector term of local plane zl into its accumulator (first record prefetched)
+  auto finish_plane = [&](int zl) {
+    if (zl >= nzl) return;
+    TC* acc = s_nl + ((zl & 1) ? plane_pts : 0);
+    const int rbeg = s_rp[zl], rend = s_rp[zl + 1];
+    if (rbeg + tid < rend) {
+      TC sum = TC(0);
+#pragma unroll
+      for (int k = 0; k < kPrefEnt; ++k) sum += eval[k] * alpha_src[ecol[k]];
+      for (int e = rc.y + kPrefEnt; e < rc.y + rc.z; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      acc[rc.x] = sum;
+    }
+    for (int r = rbeg + tid + nthr; r < rend; r += nthr) {  // more records than threads
+      const int4 rr = a.rec[r];
+      TC sum = TC(0);
+      for (int e = rr.y; e < rr.y + rr.z; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      acc[rr.x] = sum;
+    }
+  };
+  if (NL) {
+    __syncthreads();  // record offsets, alpha and the zeroed accumulators are visible
+    rc = load_record(0);
+    load_entries(rc);
+    finish_plane(0);
+    rc = load_record(1);
+  }
+
+  for (int zl = 0; zl < nzl; ++zl) {
+    const int z = z0 + zl;
+    TI* tl = s_tile + (zl & 1) * tile_elems;
+    if (NL) {
+      rn = load_record(zl + 2);
+      load_entries(rc);  // first record of plane zl + 1
+    }
+    // Veff and previous iterate of this plane, used at the end of the iteration
+    TC cv[PY], cp[PY];
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+      const int o = valid[j] ? roff[j] + nplane * z : -1;
+      cv[j] = bload<TC>(rv, boff<TC>(o, 0));
+      cp[j] = has_prev ? TC(bload<TO>(rp, boff<TO>(o, 0))) : TC(0);
+    }
+    // advance the queue; fetch plane z+R+1
 #pragma unroll
     for (int s = 0; s < Q - 1; ++s)
 #pragma unroll
       for (int j = 0; j < PY; ++j) q[s][j] = q[s + 1][j];
 #pragma unroll
     for (int j = 0; j < PY; ++j) q[Q - 1][j] = pf[j];
-    if (z + 1 < z1) {
-      const int po = plane_offset(z + 1 + R, nplane, nz, a.per_z);
+    {
+      const int po = zl + 1 < nzl ? plane_offset(z + R + 1, nplane, nz, a.per_z) : -1;
 #pragma unroll
-      for (int j = 0; j < PY; ++j) pf[j] = load_at(xv, roff[j], po);
+      for (int j = 0; j < PY; ++j) pf[j] = bload<TI>(rx, boff<TI>(roff[j], po));
     }
-
-    // epilogue operands for this plane, issued early
-    TC vpot[PY], vprev[PY];
-    int64_t gidx[PY];
-    bool valid[PY];
-#pragma unroll
-    for (int j = 0; j < PY; ++j) {
-      const int gy = y0 + ly0 + j;
-      valid[j] = active && gy < ny;
-      gidx[j] = valid[j] ? (int64_t)(x + nx * gy + nplane * z) : 0;
-      vpot[j] = valid[j] ? a.veff[gidx[j]] : TC(0);
-      vprev[j] = (valid[j] && a.prev != nullptr) ? TC(a.prev[vec * a.nd + gidx[j]]) : TC(0);
-    }
-
-    __syncthreads();  // previous plane's LDS reads are done
+    // stage plane z in LDS; fetch the halo of plane z+1
     if (active) {
 #pragma unroll
-      for (int j = 0; j < PY; ++j) lds[(R + ly0 + j) * row_stride + x] = q[R][j];
+      for (int j = 0; j < PY; ++j) tl[(R + ly0 + j) * nx + x] = q[R][j];
     }
-    {
-      const int po = (z + 1 < z1) ? plane_offset(z + 1, nplane, nz, a.per_z) : -1;
 #pragma unroll
-      for (int k = 0; k < kMaxHalo; ++k) {
-        if (hdst[k] >= 0) {
-          lds[hdst[k]] = hpf[k];
-          hpf[k] = load_at(xv, hoff[k], po);
-        }
-      }
+    for (int k = 0; k < KH; ++k)
+      if (hdst[k] >= 0) tl[hdst[k]] = hp[k];
+    {
+      const int po = zl + 1 < nzl ? plane_offset(z + 1, nplane, nz, a.per_z) : -1;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], po));
     }
     __syncthreads();
 
@@ -168,24 +262,25 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
       TC acc[PY];
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
-        const TC v = TC(q[R][j]);
-        TC t = a.c0 * v;
+        TC t = a.c0 * TC(q[R][j]);
 #pragma unroll
         for (int p = 1; p <= R; ++p) t += a.cz[p] * (TC(q[R + p][j]) + TC(q[R - p][j]));
         acc[j] = t;
       }
-      // y part: one read per LDS row of the column, shared by the PY outputs
-      TC col[PY + 2 * R];
+      // y part: each LDS row of the column is read once and feeds every row it neighbours
 #pragma unroll
-      for (int t = 0; t < PY + 2 * R; ++t) col[t] = TC(lds[(ly0 + t) * row_stride + x]);
+      for (int t = 0; t < PY + 2 * R; ++t) {
+        const TC v = TC(tl[(ly0 + t) * nx + x]);
 #pragma unroll
-      for (int j = 0; j < PY; ++j)
-#pragma unroll
-        for (int p = 1; p <= R; ++p) acc[j] += a.cy[p] * (col[R + j + p] + col[R + j - p]);
+        for (int j = 0; j < PY; ++j) {
+          const int p = t - R - j;
+          if (p != 0 && p >= -R && p <= R) acc[j] += a.cy[p < 0 ? -p : p] * v;
+        }
+      }
       // x part: neighbours inside the row
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
-        const TI* row = lds + (R + ly0 + j) * row_stride;
+        const TI* row = tl + (R + ly0 + j) * nx;
         TC t = TC(0);
         if (a.per_x) {
 #pragma unroll
@@ -206,22 +301,25 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
         }
         acc[j] += t;
       }
+      TC* nla = s_nl + ((zl & 1) ? plane_pts : 0);
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
         if (!valid[j]) continue;
         const TC v = TC(q[R][j]);
-        TC hy = acc[j] + vpot[j] * v;
-        if (a.nl_row != nullptr) {
-          const int e0 = a.nl_row[gidx[j]], e1 = a.nl_row[gidx[j] + 1];
-          TC nl = TC(0);
-          const TC* al = a.alpha + vec * a.np_tot;
-          for (int e = e0; e < e1; ++e) nl += a.nl_val[e] * al[a.nl_proj[e]];
-          hy += nl;
+        TC hy = acc[j] + cv[j] * v;
+        if (NL) {
+          const int li = (ly0 + j) * nx + x;
+          hy += nla[li];
+          nla[li] = TC(0);
         }
         TC r = a.sa * (hy - a.sc * v);
-        if (a.prev != nullptr) r += a.sb * vprev[j];
-        a.out[vec * a.nd + gidx[j]] = TO(r);
+        if (has_prev) r += a.sb * cp[j];
+        ov[roff[j] + nplane * z] = TO(r);
       }
+    }
+    if (NL) {
+      finish_plane(zl + 1);
+      rc = rn;
     }
   }
 }
@@ -229,18 +327,21 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
 HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override) {
   HxPlan best;
   double best_cost = 1e300;
+  int nyg_override = 0;
+  if (const char* e = std::getenv("CHEFSI_HX_NYG")) nyg_override = std::atoi(e);  // tiling experiments only
   const int pys[] = {1, 2, 3, 4};
   for (int py : pys) {
     if (py_override > 0 && py != py_override) continue;
     if (py_override <= 0 && elem_bytes == 8 && py > 2) continue;  // FP64 register queue budget
     for (int nyg = 1; nx * nyg <= kHxMaxThreads; ++nyg) {
+      if (nyg_override > 0 && nyg != nyg_override) continue;
       const int ty = nyg * py;
       const int nty = (ny + ty - 1) / ty;
       const int threads = nx * nyg;
       const int waves = (threads + 63) / 64;
       if (2 * radius * nx > kHxMaxHalo * waves * 64) continue;  // halo values per thread bound
-      const size_t lds = (size_t)(ty + 2 * radius) * nx * elem_bytes;
-      if (lds > 64 * 1024) continue;
+      const size_t lds = 2 * (size_t)(ty + 2 * radius) * nx * elem_bytes + 2 * (size_t)ty * nx * 8;
+      if (lds > 48 * 1024) continue;
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
       const double halo = (double)(ty + 2 * radius) / ty;
@@ -255,7 +356,8 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
         best.ty = ty;
         best.nty = nty;
         best.threads = waves * 64;
-        best.lds_bytes = lds;
+        best.kh = (2 * radius * nx <= 2 * waves * 64) ? 2 : 4;
+        best.lds_tile_bytes = lds;
       }
     }
   }
@@ -268,11 +370,39 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   return best;
 }
 
+template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
+static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, int ns, hipStream_t s) {
+  HxArgs<TI, TC, TO> a = a0;
+  a.nyg = p.nyg;
+  a.ty = p.ty;
+  a.nty = p.nty;
+  a.zc = p.zc;
+  a.nzc = p.nzc;
+  a.nblocks = (int64_t)p.nty * p.nzc * ns;
+  a.per_xcd = (int)((a.nblocks + 7) / 8);
+  size_t lds = 2 * (size_t)(p.ty + 2 * R) * a.nx * sizeof(TI);
+  a.alpha_lds = 0;
+  if (NL) {
+    lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
+    lds += 2 * (size_t)p.ty * a.nx * sizeof(TC);
+    const size_t al = (size_t)((a.np_tot + 1) & ~1) * sizeof(TC);
+    a.alpha_lds = (lds + al <= 64 * 1024) ? 1 : 0;
+    if (a.alpha_lds) lds += al;
+  }
+  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(a.per_xcd * 8));
+  hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL>), grid, dim3(p.threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TC, typename TO, int R, int PY>
 static hipError_t launch_rp(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int ns, hipStream_t s) {
-  dim3 grid((unsigned)(p.nty * p.nzc), (unsigned)ns);
-  hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY>), grid, dim3(p.threads), p.lds_bytes, s, a);
-  return hipGetLastError();
+  const bool nl = a.rec_ptr != nullptr;
+  if (p.kh <= 2)
+    return nl ? launch_final<TI, TC, TO, R, PY, 2, true>(a, p, ns, s)
+              : launch_final<TI, TC, TO, R, PY, 2, false>(a, p, ns, s);
+  return nl ? launch_final<TI, TC, TO, R, PY, 4, true>(a, p, ns, s)
+            : launch_final<TI, TC, TO, R, PY, 4, false>(a, p, ns, s);
 }
 
 template <typename TI, typename TC, typename TO, int R>

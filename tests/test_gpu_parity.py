@@ -209,13 +209,22 @@ def test_error_paths_and_handle_reuse(cs):
     with pytest.raises(cs.ChefsiError) as e:
         h.chefsi_step(Xd, ns, 4, hi, cut, lo, ws)
     assert e.value.status == cs.ERR_INVALID_ARG
-    # rank-deficient block: duplicated columns make the overlap matrix singular
+    # rank-deficient block: a zero column stays exactly zero through the filter, so the
+    # overlap matrix has an exactly zero pivot (duplicated columns would leave a pivot
+    # at rounding level whose sign is not determined)
     Xdup = X0[:, :ns].copy()
-    Xdup[:, 5] = Xdup[:, 4]
+    Xdup[:, 5] = 0.0
     with pytest.raises(cs.ChefsiError) as e:
         h.chefsi_step(dev(Xdup), ns, 4, lo, cut, hi, ws)
     assert e.value.status == cs.ERR_NOT_POSDEF
-    assert h.chefsi_last_info() > ns
+    assert h.chefsi_last_info() == ns + 6
+    # an indefinite overlap matrix given straight to the dense stage
+    Hs = dev_square(np.eye(ns))
+    Ms = dev_square(np.diag(np.r_[np.ones(ns - 1), -1.0]))
+    D = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    with pytest.raises(cs.ChefsiError) as e:
+        h.chefsi_eigh(Hs, Ms, D, ns, ws)
+    assert e.value.status == cs.ERR_NOT_POSDEF
     # the handle still works
     d = h.chefsi_step(Xd, ns, 4, lo, cut, hi, ws)
     d_ref, _ = oc.chefsi_step(prob, X0[:, :ns], 4, lo, cut, hi)
