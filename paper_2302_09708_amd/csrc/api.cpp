@@ -112,6 +112,7 @@ struct chefsi_handle {
   int* ent_col = nullptr;
   double* ent_val64 = nullptr;
   float* ent_val32 = nullptr;
+  int n_ent = 0;
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -136,6 +137,8 @@ struct WsLayout {
 };
 
 size_t elem_bytes(const chefsi_handle* h) { return h->precision == CHEFSI_FP64 ? 8 : 4; }
+
+bool plane_pts_ok(const chefsi_handle* h) { return (int64_t)h->hx_plan.ty * h->n[0] < 65536; }
 
 // Device workspace of the FP64 dense stage (Cholesky, two triangular solves for the
 // reduced matrix, symmetric eigensolve, back substitution); the calls run in sequence,
@@ -288,6 +291,7 @@ HxArgs<TI, TC, TO> hx_args(const chefsi_handle* h, const TI* x, const TO* prev, 
   a.rec = h->rec;
   a.ent_col = h->ent_col;
   a.ent_val = nl_val;
+  a.n_ent = h->n_ent;
   a.alpha = alpha;
   a.np_tot = h->np_tot;
   a.nx = h->n[0];
@@ -738,19 +742,34 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       std::vector<int> rec_pt(nrec);
       for (int64_t i = 0; i < nd; ++i)
         if (cnt[i + 1] > cnt[i]) rec_pt[rfill[key_of(i)]++] = (int)i;
+      // entries of each record padded with zeros to a multiple of 4 (one vector load each)
       std::vector<int4> recs(std::max(nrec, 1), make_int4(0, 0, 0, 0));
-      std::vector<int> ecol(std::max<int64_t>(nent, 1), 0);
-      std::vector<double> evals(std::max<int64_t>(nent, 1), 0.0);
-      int64_t e = 0;
+      std::vector<int> ecol;
+      std::vector<double> evals;
+      check(plane_pts_ok(h), "tile plane too large for 16-bit record indices");
+      check(h->np_tot < 65536, "more than 65535 projectors");
       for (int r = 0; r < nrec; ++r) {
         const int64_t i = rec_pt[r];
         const int x = (int)(i % nx), y = (int)((i / nx) % ny);
-        recs[r] = make_int4((y % hp.ty) * nx + x, (int)e, cnt[i + 1] - cnt[i], 0);
-        for (int k = cnt[i]; k < cnt[i + 1]; ++k, ++e) {
-          ecol[e] = eproj[k];
-          evals[e] = eval[k];
+        const int n = cnt[i + 1] - cnt[i];
+        const int e0 = (int)ecol.size();
+        for (int k = cnt[i]; k < cnt[i + 1]; ++k) {
+          ecol.push_back(eproj[k]);
+          evals.push_back(eval[k]);
         }
+        while (ecol.size() % 4) {
+          ecol.push_back(0);
+          evals.push_back(0.0);
+        }
+        auto col = [&](int k) { return k < n ? ecol[e0 + k] : 0; };
+        recs[r] = make_int4(((y % hp.ty) * nx + x) | (n << 16), e0, col(0) | (col(1) << 16), col(2) | (col(3) << 16));
       }
+      check(ecol.size() < ((size_t)1 << 31), "too many projector entries");
+      if (ecol.empty()) {
+        ecol.assign(4, 0);
+        evals.assign(4, 0.0);
+      }
+      h->n_ent = (int)ecol.size();
       h->rec_ptr = upload(rptr.data(), rptr.size());
       h->rec = upload(recs.data(), recs.size());
       h->ent_col = upload(ecol.data(), ecol.size());

@@ -29,9 +29,11 @@ struct HxArgs {
   const TC* veff;
   // projector records (rec_ptr == null when there are no projectors)
   const int* rec_ptr;   // nty * nz + 1: records of (tile t, plane z) are [rec_ptr[t*nz+z], rec_ptr[t*nz+z+1])
-  const int4* rec;      // {local point index ly*nx+x, first entry, entry count, 0}
-  const int* ent_col;   // alpha column of each entry
-  const TC* ent_val;    // chi value of each entry
+  const int4* rec;      // {local point ly*nx+x | entry count << 16, first entry (a multiple of 4),
+                        //  col0 | col1 << 16, col2 | col3 << 16}: alpha columns of the first 4 entries
+  const int* ent_col;   // alpha column of each entry (entries of a record padded to a multiple of 4)
+  const TC* ent_val;    // chi value of each entry (zero in the padding)
+  int n_ent;            // entries including padding
   const TC* alpha;      // ns x np_tot, projector column fastest
   int np_tot;
   int alpha_lds;        // 1: stage the block's alpha row in LDS

@@ -35,7 +35,6 @@
 namespace chefsi {
 
 constexpr unsigned kOOB = 0x80000000u;  // any buffer offset at or past the end reads as zero
-constexpr int kPrefEnt = 4;             // entries of a projector record fetched a plane ahead
 
 __device__ __forceinline__ int wrap_index(int v, int n) {
   v %= n;
@@ -172,21 +171,36 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   }
 
   // projector records: rc is this thread's first record of the plane being prepared,
-  // rn the one of the plane after it (loaded a full iteration before it is needed)
+  // rn the one of the plane after it (loaded a full iteration before it is needed);
+  // ev holds the chi values of rc's first four entries (one 16- or 32-byte load)
+  const __amdgpu_buffer_rsrc_t rrec = make_rsrc(NL ? (const void*)a.rec : (const void*)a.out,
+                                                NL ? (int64_t)(a.rec_ptr[a.nty * nz]) * 16 : 0);
+  const __amdgpu_buffer_rsrc_t rval = make_rsrc(NL ? (const void*)a.ent_val : (const void*)a.out,
+                                                NL ? (int64_t)a.n_ent * (int64_t)sizeof(TC) : 0);
   int4 rc = make_int4(0, 0, 0, 0), rn = make_int4(0, 0, 0, 0);
-  int ecol[kPrefEnt];
-  TC eval[kPrefEnt];
+  TC ev[4];
   auto load_record = [&](int zl) -> int4 {
-    if (zl >= nzl) return make_int4(0, 0, 0, 0);
-    const int r = s_rp[zl] + tid;
-    return r < s_rp[zl + 1] ? a.rec[r] : make_int4(0, 0, 0, 0);
+    const int r = zl < nzl ? s_rp[zl] + tid : 0;
+    const bool ok = zl < nzl && r < s_rp[zl + 1];
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rrec, ok ? (unsigned)r * 16u : kOOB, 0, 0);
+    return make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
   };
-  auto load_entries = [&](const int4& r) {
-#pragma unroll
-    for (int k = 0; k < kPrefEnt; ++k) {
-      const bool ok = k < r.z;
-      ecol[k] = ok ? a.ent_col[r.y + k] : 0;
-      eval[k] = ok ? a.ent_val[r.y + k] : TC(0);
+  auto load_values = [&](const int4& r) {
+    const unsigned o = (r.x >> 16) > 0 ? (unsigned)r.y * (unsigned)sizeof(TC) : kOOB;
+    if constexpr (sizeof(TC) == 4) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
+      const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+      ev[0] = __builtin_bit_cast(float, v0);
+      ev[1] = __builtin_bit_cast(float, v1);
+      ev[2] = __builtin_bit_cast(float, v2);
+      ev[3] = __builtin_bit_cast(float, v3);
+    } else {
+      const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
+      const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rval, o == kOOB ? kOOB : o + 16u, 0, 0);
+      ev[0] = __builtin_bit_cast(double, (unsigned long long)v0[0] | ((unsigned long long)v0[1] << 32));
+      ev[1] = __builtin_bit_cast(double, (unsigned long long)v0[2] | ((unsigned long long)v0[3] << 32));
+      ev[2] = __builtin_bit_cast(double, (unsigned long long)v1[0] | ((unsigned long long)v1[1] << 32));
+      ev[3] = __builtin_bit_cast(double, (unsigned long long)v1[2] | ((unsigned long long)v1[3] << 32));
     }
   };
   // sum the projector term of local plane zl into its accumulator (first record prefetched)
@@ -195,23 +209,23 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
     TC* acc = s_nl + ((zl & 1) ? plane_pts : 0);
     const int rbeg = s_rp[zl], rend = s_rp[zl + 1];
     if (rbeg + tid < rend) {
-      TC sum = TC(0);
-#pragma unroll
-      for (int k = 0; k < kPrefEnt; ++k) sum += eval[k] * alpha_src[ecol[k]];
-      for (int e = rc.y + kPrefEnt; e < rc.y + rc.z; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
-      acc[rc.x] = sum;
+      const int n = rc.x >> 16;
+      TC sum = ev[0] * alpha_src[rc.z & 0xffff] + ev[1] * alpha_src[(unsigned)rc.z >> 16] +
+               ev[2] * alpha_src[rc.w & 0xffff] + ev[3] * alpha_src[(unsigned)rc.w >> 16];
+      for (int e = rc.y + 4; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      acc[rc.x & 0xffff] = sum;
     }
     for (int r = rbeg + tid + nthr; r < rend; r += nthr) {  // more records than threads
       const int4 rr = a.rec[r];
       TC sum = TC(0);
-      for (int e = rr.y; e < rr.y + rr.z; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
-      acc[rr.x] = sum;
+      for (int e = rr.y; e < rr.y + (rr.x >> 16); ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      acc[rr.x & 0xffff] = sum;
     }
   };
   if (NL) {
     __syncthreads();  // record offsets, alpha and the zeroed accumulators are visible
     rc = load_record(0);
-    load_entries(rc);
+    load_values(rc);
     finish_plane(0);
     rc = load_record(1);
   }
@@ -221,7 +235,7 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
     TI* tl = s_tile + (zl & 1) * tile_elems;
     if (NL) {
       rn = load_record(zl + 2);
-      load_entries(rc);  // first record of plane zl + 1
+      load_values(rc);  // first record of plane zl + 1
     }
     // Veff and previous iterate of this plane, used at the end of the iteration
     TC cv[PY], cp[PY];
@@ -332,7 +346,7 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   const int pys[] = {1, 2, 3, 4};
   for (int py : pys) {
     if (py_override > 0 && py != py_override) continue;
-    if (py_override <= 0 && elem_bytes == 8 && py > 2) continue;  // FP64 register queue budget
+    if (py_override <= 0 && py > 2) continue;  // register queue budget (measured: PY 3-4 lose occupancy)
     for (int nyg = 1; nx * nyg <= kHxMaxThreads; ++nyg) {
       if (nyg_override > 0 && nyg != nyg_override) continue;
       const int ty = nyg * py;
