@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hx_apply_cfg2_fp64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hx_apply_cfg2_fp64_traffic.txt")
 
 
 def parse():
@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-columns", type=int, default=8)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="after the timed steps, run one plain device copy of 1 GiB (counter calibration)")
     return p.parse_args()
 
 
@@ -142,6 +144,12 @@ def main():
         kern[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                       "avg_launch_ms": ms / n if n else 0.0}
     h.chefsi_profile_enable(False)
+    if args.calibrate_copy:  # a plain copy kernel of known size: reads and writes 1 GiB
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # algorithmic bytes of hx_apply per step: (3m + 1) arrays of Nd x Ns plus Veff per launch
     hx_bytes_step = (3 * m + 1) * prob.nd * ns * b + (m + 1) * prob.nd * b

@@ -2,9 +2,10 @@
 //
 // For every atom J, projector a and orbital v:
 //   alpha[v][poff_J + a] = gamma_Ja * dV * sum_{s in S_J} chi_J[s, a] * y_v[S_J[s]]
-// The paper does this as one dense product per atom (chi_J^T X[S_J]); here a
-// wave64 owns one (atom, orbital) pair, streams the atom's support once and
-// reduces across lanes in a fixed order (deterministic, no atomics).  The
+// The paper does this as one dense product per atom (chi_J^T X[S_J]).  Here a wave64
+// owns one atom and kV orbitals: it streams the atom's support indices and chi values
+// once, gathers the kV orbitals at those points (kV independent loads in flight per
+// step), and reduces across lanes in a fixed order (deterministic, no atomics).  The
 // scatter half, y[S_J] += chi_J alpha_J, is fused into hx_apply.
 #include "common.h"
 
@@ -17,38 +18,57 @@ __device__ __forceinline__ TC wave_sum(TC v) {
   return v;
 }
 
+constexpr int kNlWaves = 4;  // waves per block (same atom, consecutive orbital groups)
+constexpr int kNlV = 4;      // orbitals per wave
+constexpr int kNlP = 4;      // projectors per pass
+
 template <typename TI, typename TC>
 __global__ __launch_bounds__(256) void nl_project_kernel(NlArgs<TI, TC> a) {
-  constexpr int kWaves = 4;
-  constexpr int kP = 4;  // projectors per pass
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int atom = blockIdx.x;
-  const int64_t vec = (int64_t)blockIdx.y * kWaves + wave;
-  if (vec >= a.ns) return;  // whole wave exits together; no block barrier below
+  const int64_t v0 = ((int64_t)blockIdx.y * kNlWaves + wave) * kNlV;
+  if (v0 >= a.ns) return;  // whole wave exits together; no block barrier below
   const int s0 = a.supp_off[atom];
   const int n = a.supp_off[atom + 1] - s0;
   const int npj = a.nproj[atom];
   const TC* chi = a.chi + a.chi_off[atom];
   const int* idx = a.supp_idx + s0;
-  const TI* y = a.y + vec * a.nd;
-  for (int a0 = 0; a0 < npj; a0 += kP) {
-    TC acc[kP];
+  const TI* y[kNlV];
+  bool vok[kNlV];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = TC(0);
+  for (int u = 0; u < kNlV; ++u) {
+    vok[u] = v0 + u < a.ns;
+    y[u] = a.y + (vok[u] ? v0 + u : v0) * a.nd;
+  }
+  for (int a0 = 0; a0 < npj; a0 += kNlP) {
+    TC acc[kNlV][kNlP];
+#pragma unroll
+    for (int u = 0; u < kNlV; ++u)
+#pragma unroll
+      for (int p = 0; p < kNlP; ++p) acc[u][p] = TC(0);
     for (int s = lane; s < n; s += 64) {
-      const TC v = TC(y[idx[s]]);
+      const int i = idx[s];
+      TC c[kNlP];
 #pragma unroll
-      for (int p = 0; p < kP; ++p)
-        if (a0 + p < npj) acc[p] += chi[(int64_t)(a0 + p) * n + s] * v;
+      for (int p = 0; p < kNlP; ++p) c[p] = a0 + p < npj ? chi[(int64_t)(a0 + p) * n + s] : TC(0);
+      TC yv[kNlV];
+#pragma unroll
+      for (int u = 0; u < kNlV; ++u) yv[u] = TC(y[u][i]);
+#pragma unroll
+      for (int u = 0; u < kNlV; ++u)
+#pragma unroll
+        for (int p = 0; p < kNlP; ++p) acc[u][p] += c[p] * yv[u];
     }
 #pragma unroll
-    for (int p = 0; p < kP; ++p) {
-      if (a0 + p < npj) {
-        const TC t = wave_sum(acc[p]);
-        if (lane == 0) {
+    for (int u = 0; u < kNlV; ++u) {
+#pragma unroll
+      for (int p = 0; p < kNlP; ++p) {
+        if (a0 + p >= npj) continue;
+        const TC t = wave_sum(acc[u][p]);
+        if (lane == 0 && vok[u]) {
           const int q = a.poff[atom] + a0 + p;
-          a.alpha[vec * a.np_tot + q] = a.gdv[q] * t;
+          a.alpha[(v0 + u) * a.np_tot + q] = a.gdv[q] * t;
         }
       }
     }
@@ -58,8 +78,9 @@ __global__ __launch_bounds__(256) void nl_project_kernel(NlArgs<TI, TC> a) {
 template <typename TI, typename TC>
 hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s) {
   if (a.n_atoms <= 0 || a.ns <= 0) return hipSuccess;
-  dim3 grid((unsigned)a.n_atoms, (unsigned)((a.ns + 3) / 4));
-  hipLaunchKernelGGL((nl_project_kernel<TI, TC>), grid, dim3(256), 0, s, a);
+  const int per_block = kNlWaves * kNlV;
+  dim3 grid((unsigned)a.n_atoms, (unsigned)((a.ns + per_block - 1) / per_block));
+  hipLaunchKernelGGL((nl_project_kernel<TI, TC>), grid, dim3(64 * kNlWaves), 0, s, a);
   return hipGetLastError();
 }
 
