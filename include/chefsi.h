@@ -65,6 +65,13 @@ typedef enum {
   CHEFSI_ERR_OOM = 8           /* a library-internal allocation failed (create only)               */
 } chefsi_status;
 
+/* Arithmetic of a handle's steps (the dense eigensolve is FP64 in both):
+ *   CHEFSI_FP64   X in double; filter, projection and rotation in FP64 (FP64 MFMA).
+ *   CHEFSI_MIXED  X in float; filter in FP32; projection and rotation as split
+ *                 bf16 products on MFMA (each FP32 value as hi + lo bf16, three
+ *                 bf16 products, FP32 accumulation; Hs and Ms summed in FP64
+ *                 over K chunks); Cholesky, eigensolve and chefsi_refine_fp64
+ *                 in FP64. */
 typedef enum { CHEFSI_FP64 = 0, CHEFSI_MIXED = 1 } chefsi_precision;
 
 typedef struct chefsi_handle chefsi_handle_t;
@@ -173,12 +180,18 @@ int chefsi_solve(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, int32_
                  void* ws, size_t ws_bytes, void* stream, double* ritz_host,
                  double* lam_lo_out, double* lam_cut_out);
 
-/* Final FP64 Rayleigh-Ritz pass for a CHEFSI_MIXED handle (X is FP32): forms
- * Hs = X^T (H X) and Ms = X^T X with FP64 arithmetic from the FP32 block,
- * solves the FP64 subspace problem, rotates X in FP64 (stored back as FP32)
- * and returns the FP64 Ritz values.  On a CHEFSI_FP64 handle it is one
- * Rayleigh-Ritz pass with no filtering. */
-int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns,
+/* Final FP64 Rayleigh-Ritz pass (the mixed-precision path ends with it; the
+ * paper's own steps are FP64 throughout, Sec. 2).  With degree > 0 the block is
+ * first filtered (Alg. 1, Filtering; storage precision, bounds as for
+ * chefsi_filter), which also damps what the split-bf16 rotation of the previous
+ * step left outside the wanted subspace; degree == 0 skips the filter and
+ * ignores the bounds.  Then Hs = X^T (H X) and Ms = X^T X are formed with FP64
+ * arithmetic from the stored block, the FP64 subspace problem is solved, X is
+ * rotated in FP64 (stored back once rounded to the handle's element type) and
+ * ritz_host (HOST, ns doubles) receives the FP64 Ritz values.  On a
+ * CHEFSI_FP64 handle with degree > 0 this equals chefsi_step. */
+int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree,
+                       double lam_lo, double lam_cut, double lam_hi,
                        void* ws, size_t ws_bytes, void* stream, double* ritz_host);
 
 /* Per-kernel timing with HIP events recorded on the call's stream around every

@@ -87,7 +87,7 @@ def load(path: str = LIB_PATH):
     lib.chefsi_rotate.argtypes = [vp, vp, vp, i32, vp, sz, vp]
     lib.chefsi_step.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd]
     lib.chefsi_solve.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd, pd, pd]
-    lib.chefsi_refine_fp64.argtypes = [vp, vp, i32, vp, sz, vp, pd]
+    lib.chefsi_refine_fp64.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd]
     lib.chefsi_profile_enable.argtypes = [vp, i32]
     lib.chefsi_profile_reset.argtypes = [vp]
     lib.chefsi_profile_read.argtypes = [vp, i32, pd, C.POINTER(C.c_int64)]
@@ -223,11 +223,27 @@ class Handle:
                                            C.byref(lo), C.byref(cut)))
         return ritz, lo.value, cut.value
 
-    def chefsi_refine_fp64(self, X, ns, ws, ws_bytes=None, stream=None) -> np.ndarray:
+    def chefsi_refine_fp64(self, X, ns, ws, degree=0, lam_lo=0.0, lam_cut=0.0, lam_hi=0.0, ws_bytes=None,
+                           stream=None) -> np.ndarray:
         ritz = np.zeros(int(ns))
-        self._check(self._lib.chefsi_refine_fp64(self.h, _ptr(X), int(ns), _ptr(ws), self._wsb(ws, ws_bytes),
+        self._check(self._lib.chefsi_refine_fp64(self.h, _ptr(X), int(ns), int(degree), float(lam_lo),
+                                                 float(lam_cut), float(lam_hi), _ptr(ws), self._wsb(ws, ws_bytes),
                                                  _stream(stream), ritz.ctypes.data_as(C.POINTER(C.c_double))))
         return ritz
+
+    def solve(self, X, ns, degree, n_iter, ws, bounds=None, stream=None):
+        """n_iter CheFSI iterations with the bounds update lam_lo <- D_1, lam_cut <- D_ns.
+
+        FP64 handle: n_iter chefsi_step calls.  Mixed handle: n_iter - 1 mixed steps,
+        then chefsi_refine_fp64 with the same degree (filter + FP64 Rayleigh-Ritz), so
+        both precisions apply the filter n_iter times.  Returns (ritz, lam_lo, lam_cut)."""
+        lo, cut, hi = bounds if bounds is not None else self.chefsi_spectral_bounds()
+        if self.precision == FP64:
+            return self.chefsi_solve(X, ns, degree, n_iter, lo, cut, hi, ws, stream=stream)
+        if n_iter > 1:
+            _, lo, cut = self.chefsi_solve(X, ns, degree, n_iter - 1, lo, cut, hi, ws, stream=stream)
+        ritz = self.chefsi_refine_fp64(X, ns, ws, degree, lo, cut, hi, stream=stream)
+        return ritz, float(ritz[0]), float(ritz[-1])
 
     def chefsi_profile_enable(self, on: bool = True):
         self._check(self._lib.chefsi_profile_enable(self.h, 1 if on else 0))

@@ -12,6 +12,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -131,7 +132,7 @@ struct chefsi_handle {
 namespace {
 
 struct WsLayout {
-  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, partial = 0, solver = 0, total = 0;
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, partial = 0, zsplit = 0, solver = 0, total = 0;
   size_t bufB_bytes = 0, solver_bytes = 0;
   GramPlan gram;
 };
@@ -197,6 +198,8 @@ WsLayout layout(chefsi_handle* h, int ns) {
   L.gram = plan_gram(h->nd, ns);
   L.partial = off;
   off += align256(L.gram.partial_bytes);
+  L.zsplit = off;
+  if (h->precision == CHEFSI_MIXED) off += align256(zsplit_bytes(ns));
   L.solver = off;
   L.solver_bytes = solver_workspace(h, ns);
   off += align256(std::max<size_t>(L.solver_bytes, 256));
@@ -392,14 +395,27 @@ T* run_filter(chefsi_handle* h, T* A, T* B, int ns, int m, double lo, double cut
   return cur;
 }
 
+// Arithmetic of the dense products: FP64 MFMA, or split bf16 (three bf16 MFMAs per
+// product, FP32 accumulation) for the FP32 blocks of a mixed handle.
+enum class Gemm { F64, BF16X3 };
+
+template <typename TX, typename TY>
+hipError_t gram_launch(Gemm g, const TX* X, const TY* Y, int64_t nd, int ns, const GramPlan& p, double* part,
+                       hipStream_t s) {
+  if constexpr (std::is_same<TX, float>::value && std::is_same<TY, float>::value) {
+    if (g == Gemm::BF16X3) return launch_gram_bf16x3(X, Y, nd, ns, p, part, s);
+  }
+  return launch_gram_f64<TX, TY>(X, Y, nd, ns, p, part, s);
+}
+
 // Hs = X^T Y, Ms = X^T X (full symmetric, FP64), via split-K partial tiles.
 template <typename TX, typename TY>
 void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayout& L, void* ws, double* Hs,
-               double* Ms, hipStream_t s) {
+               double* Ms, hipStream_t s, Gemm g) {
   double* part = at<double>(ws, L.partial);
   {
     ProfScope ps(h, P_GRAM, s);
-    HIP_TRY((launch_gram_f64<TX, TY>(X, Y, h->nd, ns, L.gram, part, s)));
+    HIP_TRY((gram_launch<TX, TY>(g, X, Y, h->nd, ns, L.gram, part, s)));
     ps.done();
   }
   {
@@ -409,7 +425,7 @@ void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayou
   }
   {
     ProfScope ps(h, P_GRAM, s);
-    HIP_TRY((launch_gram_f64<TX, TX>(X, X, h->nd, ns, L.gram, part, s)));
+    HIP_TRY((gram_launch<TX, TX>(g, X, X, h->nd, ns, L.gram, part, s)));
     ps.done();
   }
   {
@@ -471,11 +487,22 @@ void copy_block(chefsi_handle* h, T* dst, const T* src, int ns, hipStream_t s) {
 }
 
 template <typename T>
-void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hipStream_t s) {
+void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hipStream_t s, Gemm g, void* ws,
+                 const WsLayout& L) {
   ProfScope ps(h, P_ROT, s);
+  if constexpr (std::is_same<T, float>::value) {
+    if (g == Gemm::BF16X3) {
+      HIP_TRY(launch_rotate_bf16x3(X, Z, at<void>(ws, L.zsplit), O, h->nd, ns, s));
+      ps.done();
+      return;
+    }
+  }
   HIP_TRY((launch_rotate_f64<T, T>(X, Z, O, h->nd, ns, s)));
   ps.done();
 }
+
+// The dense-product arithmetic of a handle's own steps.
+Gemm step_gemm(const chefsi_handle* h) { return h->precision == CHEFSI_MIXED ? Gemm::BF16X3 : Gemm::F64; }
 
 void ritz_to_host(chefsi_handle* h, const double* D, int ns, double* ritz_host, void* ws, const WsLayout& L,
                   hipStream_t s) {
@@ -503,26 +530,33 @@ void step_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, dou
   T* Xf = run_filter<T>(h, A, B, ns, m, lo, cut, hi, alpha, s);
   T* Yf = Xf == A ? B : A;
   apply_fused<T, T, T>(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
-  gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s);
+  gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s, step_gemm(h));
   dense_eig(h, Hs, Ms, D, ns, L, ws, s);
-  rotate_into<T>(h, Xf, Hs, Yf, ns, s);  // Y~ is dead: X = X~ Z~ goes there
+  rotate_into<T>(h, Xf, Hs, Yf, ns, s, step_gemm(h), ws, L);  // Y~ is dead: X = X~ Z~ goes there
   if (Yf != X) copy_block<T>(h, X, Yf, ns, s);
   ritz_to_host(h, D, ns, ritz_host, ws, L, s);
 }
 
-// FP64 Rayleigh-Ritz on the block X (no filter): FP64 arithmetic whatever the storage type.
+// Optional filter of degree m (storage precision), then a Rayleigh-Ritz pass with FP64
+// arithmetic whatever the storage type: H X in FP64 from the stored block, FP64 Gram
+// products, the FP64 dense stage and an FP64 rotation rounded once to the storage type.
 template <typename T>
-void refine_impl(chefsi_handle* h, T* X, int ns, void* ws, const WsLayout& L, hipStream_t s, double* ritz_host) {
+void refine_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, double hi, void* ws,
+                 const WsLayout& L, hipStream_t s, double* ritz_host) {
+  if (m > 0) {
+    T* r = run_filter<T>(h, X, at<T>(ws, L.bufB), ns, m, lo, cut, hi, at<T>(ws, L.alpha), s);
+    if (r != X) copy_block<T>(h, X, r, ns, s);
+  }
   double* HX = at<double>(ws, L.bufB);  // Nd x ns FP64
   double* alpha = at<double>(ws, L.alpha);
   double* Hs = at<double>(ws, L.hs);
   double* Ms = at<double>(ws, L.ms);
   double* D = at<double>(ws, L.d);
   apply_fused<T, double, double>(h, X, nullptr, HX, ns, 1.0, 0.0, 0.0, alpha, s);
-  gram_pair<T, double>(h, X, HX, ns, L, ws, Hs, Ms, s);
+  gram_pair<T, double>(h, X, HX, ns, L, ws, Hs, Ms, s, Gemm::F64);
   dense_eig(h, Hs, Ms, D, ns, L, ws, s);
   T* B = at<T>(ws, L.bufB);
-  rotate_into<T>(h, X, Hs, B, ns, s);
+  rotate_into<T>(h, X, Hs, B, ns, s, Gemm::F64, ws, L);
   copy_block<T>(h, X, B, ns, s);
   ritz_to_host(h, D, ns, ritz_host, ws, L, s);
 }
@@ -910,12 +944,12 @@ int chefsi_project(chefsi_handle_t* h, const void* X, int32_t ns, double* Hs, do
       double* Y = at<double>(ws, L.bufB);
       apply_fused<double, double, double>(h, (const double*)X, nullptr, Y, ns, 1.0, 0.0, 0.0,
                                           at<double>(ws, L.alpha), s);
-      gram_pair<double, double>(h, (const double*)X, Y, ns, L, ws, Hs, Ms, s);
+      gram_pair<double, double>(h, (const double*)X, Y, ns, L, ws, Hs, Ms, s, Gemm::F64);
     } else {
       float* Y = at<float>(ws, L.bufB);
       apply_fused<float, float, float>(h, (const float*)X, nullptr, Y, ns, 1.0, 0.0, 0.0, at<float>(ws, L.alpha),
                                        s);
-      gram_pair<float, float>(h, (const float*)X, Y, ns, L, ws, Hs, Ms, s);
+      gram_pair<float, float>(h, (const float*)X, Y, ns, L, ws, Hs, Ms, s, Gemm::BF16X3);
     }
   });
 }
@@ -943,11 +977,11 @@ int chefsi_rotate(chefsi_handle_t* h, void* X, const double* Z, int32_t ns, void
     hipStream_t s = (hipStream_t)stream;
     if (h->precision == CHEFSI_FP64) {
       double* B = at<double>(ws, L.bufB);
-      rotate_into<double>(h, (const double*)X, Z, B, ns, s);
+      rotate_into<double>(h, (const double*)X, Z, B, ns, s, Gemm::F64, ws, L);
       copy_block<double>(h, (double*)X, B, ns, s);
     } else {
       float* B = at<float>(ws, L.bufB);
-      rotate_into<float>(h, (const float*)X, Z, B, ns, s);
+      rotate_into<float>(h, (const float*)X, Z, B, ns, s, Gemm::BF16X3, ws, L);
       copy_block<float>(h, (float*)X, B, ns, s);
     }
   });
@@ -998,18 +1032,20 @@ int chefsi_solve(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, int32_
   });
 }
 
-int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
-                       double* ritz_host) {
+int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
+                       double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host) {
   return guarded(h, [&] {
     check(X != nullptr, "X is NULL");
+    check(degree >= 0, "degree must be >= 0");
     check_ns(h, ns);
+    if (degree > 0) check_bounds(lam_lo, lam_cut, lam_hi);
     WsLayout L;
     check_ws(h, ns, ws, ws_bytes, L);
     hipStream_t s = (hipStream_t)stream;
     if (h->precision == CHEFSI_FP64)
-      refine_impl<double>(h, (double*)X, ns, ws, L, s, ritz_host);
+      refine_impl<double>(h, (double*)X, ns, degree, lam_lo, lam_cut, lam_hi, ws, L, s, ritz_host);
     else
-      refine_impl<float>(h, (float*)X, ns, ws, L, s, ritz_host);
+      refine_impl<float>(h, (float*)X, ns, degree, lam_lo, lam_cut, lam_hi, ws, L, s, ritz_host);
   });
 }
 

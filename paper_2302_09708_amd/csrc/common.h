@@ -122,4 +122,13 @@ hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, 
 template <typename TX, typename TO>
 hipError_t launch_rotate_f64(const TX* X, const double* Z, TO* O, int64_t nd, int ns, hipStream_t s);
 
+// Split-bf16 variants for FP32 blocks (three bf16 MFMAs per product, FP32 accumulation).
+// gram: same plan, partial layout and reduction as the FP64 kernel.
+// rotate: Z (FP64) is first split into the zsplit scratch (zsplit_bytes(ns) bytes).
+hipError_t launch_gram_bf16x3(const float* A, const float* B, int64_t nd, int ns, const GramPlan& p,
+                              double* partial, hipStream_t s);
+size_t zsplit_bytes(int ns);
+hipError_t launch_rotate_bf16x3(const float* X, const double* Z, void* zsplit, float* O, int64_t nd, int ns,
+                                hipStream_t s);
+
 }  // namespace chefsi

@@ -97,6 +97,13 @@ CONFIGS: Dict[str, Config] = {
     # Large metallic cell, 120^3 periodic, h = 0.22, 1000 atoms from a jittered FCC 7^3 lattice.
     "cfg4": Config("cfg4", (120, 120, 120), (0.22, 0.22, 0.22), (0, 0, 0), "fcc_subset", 1000, 4,
                    7200, 16, 4, 1004, 2004, lattice_cells=(7, 7, 7)),
+    # Reduced twin of cfg3 (half the grid per direction, an eighth of the atoms, Ns 300):
+    # small enough for the FP64 oracle to run whole iterations on the host.
+    "cfg3_twin": Config("cfg3_twin", (30, 30, 90), (0.3, 0.3, 0.3), (0, 0, 1), "slab", 25, 4,
+                        300, 24, 6, 1013, 2013, lattice_cells=(3, 3, 3)),
+    # Test-sized slab (same recipe), for mixed/FP64 parity of whole iterations.
+    "slab_small": Config("slab_small", (16, 16, 48), (0.3, 0.3, 0.3), (0, 0, 1), "slab", 6, 4,
+                         48, 24, 6, 1023, 2023, lattice_cells=(2, 2, 2)),
 }
 
 WELL_DEPTH = 2.0     # Ha
