@@ -9,9 +9,10 @@ periodic 72^3 grid (h = 0.25 bohr, FD order 12), 128 atoms with s + 3p
 Kleinman-Bylander projectors, Ns = 600, Chebyshev degree 20, plain FP64.
 
 Prints ONE JSON line with iterations/s, the roofline position of the dominant
-kernel (timed with HIP events recorded by the library on its launch stream)
-and, at N = 1, the FP64 CPU oracle timed on a bounded sample of the same
-workload on this host's cores.
+kernel (timed with HIP events recorded by the library on its launch stream),
+the other precision on the same inputs ("compare": FP64 vs mixed) and, at
+N = 1, the FP64 CPU oracle timed on a bounded sample of the same workload on
+this host's cores.
 """
 from __future__ import annotations
 
@@ -29,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
+BF16_MFMA_PEAK_TFS = 2500.0    # MI355X dense BF16 matrix
+KERNELS = ["hx_apply", "nl_project", "gram", "gram_reduce", "rotate", "dense_eig", "copy"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hx_apply_cfg2_fp64_traffic.txt")
 
 
@@ -40,6 +43,10 @@ def parse():
     p.add_argument("--workload", default="cfg2")
     p.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-compare", action="store_true", help="skip the other precision on the same inputs")
+    p.add_argument("--requests", type=int, default=256, help="cfg5: number of requests")
+    p.add_argument("--slots", type=int, default=4, help="cfg5: concurrent solves")
+    p.add_argument("--calibration", type=int, default=16, help="cfg5: requests solved alone to set the rate")
     p.add_argument("--cpu-columns", type=int, default=8)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="after the timed steps, run one plain device copy of 1 GiB (counter calibration)")
@@ -97,33 +104,39 @@ def cpu_baseline(prob, cfg, ns_cols: int):
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is design only",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2302_09708_amd import chefsi as cs
-    from paper_2302_09708_amd import inputs
+def gemm_figures(nd: int, ns: int, prec: int, gram_ms: float, rot_ms: float, fp64: bool):
+    """Algorithmic and executed MFMA flops of one step's projection (two Gram products) and rotation."""
+    alg = 2.0 * nd * ns * (ns + 1) * 2 + 2.0 * nd * ns * ns
+    nt = (ns + 127) // 128
+    gram_exec = 2 * (2.0 * nd * 128 * 128 * nt * (nt + 1) // 2)      # upper 128 x 128 tiles only
+    if fp64:
+        rot_exec = 2.0 * nd * ns * ns
+        mult, peak, unit_dtype = 1, FP64_MFMA_PEAK_TFS, "f64"
+    else:
+        ld = (ns + 31) // 32 * 32
+        cols = (ns + 127) // 128 * 128
+        rot_exec = 2.0 * ((nd + 255) // 256 * 256) * cols * ld
+        mult, peak, unit_dtype = 3, BF16_MFMA_PEAK_TFS, "bf16"   # three bf16 products per FP32 product
+    t = (gram_ms + rot_ms) * 1e-3
+    executed = mult * (gram_exec + rot_exec)
+    return {"algorithmic_tflops": alg / t / 1e12, "executed_tflops": executed / t / 1e12, "mfma_dtype": unit_dtype,
+            "peak_tflops": peak, "utilisation": executed / t / 1e12 / peak,
+            "gram_executed_tflops": mult * gram_exec / (gram_ms * 1e-3) / 1e12,
+            "rotate_executed_tflops": mult * rot_exec / (rot_ms * 1e-3) / 1e12}
 
-    cfg = inputs.CONFIGS[args.workload]
-    precision = args.precision or ("fp64" if args.workload in ("cfg1", "cfg2") else "mixed")
+
+def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
+    """Time `steps` CheFSI steps of one precision on the workload; per-kernel HIP-event times."""
+    import torch
     prec = cs.FP64 if precision == "fp64" else cs.MIXED
     tdt = torch.float64 if prec == cs.FP64 else torch.float32
-    b = 8 if prec == cs.FP64 else 4
-    prob = inputs.make_problem(cfg)
     ns, m = cfg.ns, cfg.degree
-    print(f"[bench] {cfg.name} Nd={prob.nd} Ns={ns} degree={m} {precision}", file=sys.stderr, flush=True)
-    x0 = inputs.initial_block(prob.nd, ns, cfg.x_seed)
     h = cs.Handle(prob, precision=prec, max_ns=ns)
     ws = cs.workspace(h, ns)
     X = torch.from_numpy(x0).to(device="cuda", dtype=tdt)
-    del x0
     lo, cut, hi = h.chefsi_spectral_bounds()
     stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         d = h.chefsi_step(X, ns, m, lo, cut, hi, ws, stream=stream)
         lo, cut = float(d[0]), float(d[-1])
     torch.cuda.synchronize()
@@ -131,19 +144,116 @@ def main():
     h.chefsi_profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         d = h.chefsi_step(X, ns, m, lo, cut, hi, ws, stream=stream)
         lo, cut = float(d[0]), float(d[-1])
-        print(f"[bench] step {i + 1}/{args.steps} D1={d[0]:.6f}", file=sys.stderr, flush=True)
+        print(f"[bench] {precision} step {i + 1}/{steps} D1={d[0]:.6f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    names = ["hx_apply", "nl_project", "gram", "gram_reduce", "rotate", "dense_eig", "copy"]
     kern = {}
-    for kid, name in enumerate(names):
+    for kid, name in enumerate(KERNELS):
         ms, n = h.chefsi_profile_read(kid)
-        kern[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
-                      "avg_launch_ms": ms / n if n else 0.0}
+        kern[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_launch_ms": ms / n if n else 0.0}
+    h.chefsi_profile_reset()
+    refine_ms = None
+    if prec == cs.MIXED:  # the once-per-solve FP64 refinement (filter + FP64 Rayleigh-Ritz), timed once
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h.chefsi_refine_fp64(X, ns, ws, m, lo, cut, hi, stream=stream)
+        torch.cuda.synchronize()
+        refine_ms = (time.perf_counter() - t1) * 1e3
     h.chefsi_profile_enable(False)
+    del X, ws
+    b = 8 if prec == cs.FP64 else 4
+    hx_bytes_step = (3 * m + 1) * prob.nd * ns * b + (m + 1) * prob.nd * b
+    hx_ms = kern["hx_apply"]["ms_per_step"]
+    out = {"precision": precision, "iter_per_s": steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+           "hx_gbs": hx_bytes_step / (hx_ms * 1e-3) / 1e9, "hx_bytes_step": hx_bytes_step, "kernels": kern,
+           "gemm": gemm_figures(prob.nd, ns, prec, kern["gram"]["ms_per_step"] + kern["gram_reduce"]["ms_per_step"],
+                                kern["rotate"]["ms_per_step"], prec == cs.FP64)}
+    if refine_ms is not None:
+        out["refine_ms"] = refine_ms
+        # a solve of n_iter filter passes: n_iter - 1 mixed steps + the refinement
+        out["solve_ms"] = (cfg.n_iter - 1) * out["ms_per_step"] + refine_ms
+    else:
+        out["solve_ms"] = cfg.n_iter * out["ms_per_step"]
+    return out
+
+
+def serving_bench(args):
+    """Serving stream: Poisson arrivals of CheFSI solve requests of mixed sizes, continuous
+    admission by slot and HBM footprint; p50/p99 latency and solves/s."""
+    import torch
+    from paper_2302_09708_amd import chefsi as cs
+    from paper_2302_09708_amd import inputs, serving
+
+    n_req = args.requests
+    t0 = time.perf_counter()
+    specs = []
+    for k in range(n_req):
+        prob, ns, degree, seed = inputs.serving_request(k)
+        specs.append((prob, ns, degree, seed))
+        if (k + 1) % 32 == 0:
+            print(f"[bench] generated {k + 1}/{n_req} requests ({time.perf_counter() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    o, r, c = serving.gpu_ops(cs.MIXED)
+
+    def reqs(idx, arrivals):
+        return [serving.Request(rid=k, prob=specs[k][0], ns=specs[k][1], degree=specs[k][2], n_iter=10,
+                                x_seed=specs[k][3], arrival=float(a)) for k, a in zip(idx, arrivals)]
+
+    # warm-up and calibration: requests solved alone, one after another
+    serving.Scheduler(budget, 1, o, r, c).run(reqs([0], [0.0]))
+    n_cal = min(args.calibration, n_req)
+    cal = serving.Scheduler(budget, 1, o, r, c).run(reqs(range(n_cal), [0.0] * n_cal))
+    solo = float(np.mean([x.finished - x.admitted for x in cal]))
+    rate = 0.8 / solo
+    print(f"[bench] mean solo solve {solo * 1e3:.1f} ms -> arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
+    arrivals = serving.poisson_arrivals(n_req, rate, seed=5000)
+    sched = serving.Scheduler(budget, args.slots, o, r, c)
+    res = sched.run(reqs(range(n_req), arrivals))
+    st = serving.summarize(res)
+    out = {
+        "metric": "serving solves/s", "value": st["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32+bf16x3+f64", "data": "synthetic",
+        "config": {"workload": f"cfg5: {n_req} requests, Poisson arrivals at 0.8 / mean solo solve time, "
+                               "cubic N ~ U{24..64}, h 0.3, 8-96 atoms x 4 projectors, Ns ~ U{40..400}, "
+                               "periodic or Dirichlet-z slab 50/50, degree 20, 10 iterations (9 mixed + refine)",
+                   "slots": args.slots, "hbm_budget_bytes": budget},
+        "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_latency_s": st["mean_s"], "makespan_s": st["makespan_s"],
+        "mean_solo_solve_s": solo, "arrival_rate_per_s": rate, "peak_admitted_bytes": sched.peak_bytes,
+        "peak_concurrent": sched.peak_active,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is design only",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "cfg5":
+        serving_bench(args)
+        return
+    import torch
+    from paper_2302_09708_amd import chefsi as cs
+    from paper_2302_09708_amd import inputs
+
+    cfg = inputs.CONFIGS[args.workload]
+    precision = args.precision or ("fp64" if args.workload in ("cfg1", "cfg2") else "mixed")
+    prob = inputs.make_problem(cfg)
+    ns, m = cfg.ns, cfg.degree
+    print(f"[bench] {cfg.name} Nd={prob.nd} Ns={ns} degree={m} {precision}", file=sys.stderr, flush=True)
+    x0 = inputs.initial_block(prob.nd, ns, cfg.x_seed)
+    main_run = run_path(cs, prob, cfg, precision, args.steps, args.warmup, x0)
+    other = None
+    if not args.no_compare:  # the other precision on the same inputs
+        other_prec = "mixed" if precision == "fp64" else "fp64"
+        other = run_path(cs, prob, cfg, other_prec, args.steps, args.warmup, x0)
+    del x0
     if args.calibrate_copy:  # a plain copy kernel of known size: reads and writes 1 GiB
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -151,52 +261,60 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # algorithmic bytes of hx_apply per step: (3m + 1) arrays of Nd x Ns plus Veff per launch
-    hx_bytes_step = (3 * m + 1) * prob.nd * ns * b + (m + 1) * prob.nd * b
-    hx_launches = m + 1
-    hx_ms = kern["hx_apply"]["ms_per_step"]
-    hx_gbs = hx_bytes_step / (hx_ms * 1e-3) / 1e9
-    gemm_flops_step = 2.0 * prob.nd * ns * (ns + 1) * 2 + 2.0 * prob.nd * ns * ns
-    gemm_ms = kern["gram"]["ms_per_step"] + kern["gram_reduce"]["ms_per_step"] + kern["rotate"]["ms_per_step"]
-    gemm_tfs = gemm_flops_step / (gemm_ms * 1e-3) / 1e12
+    kern = main_run["kernels"]
     dominant = max(kern, key=lambda k: kern[k]["ms_per_step"])
-
     traffic = None
     if os.path.exists(TRAFFIC_FILE) and precision == "fp64" and cfg.name == "cfg2":
         t = json.load(open(TRAFFIC_FILE))
         if t.get("source_sha256_16") == kernel_source_hash("hx_apply.hip"):
             traffic = t.get("bytes_per_launch")
+    g = main_run["gemm"]
     if dominant in ("gram", "rotate"):
-        roof = {"bound": "mfma", "kernel": dominant, "achieved": gemm_tfs, "peak": FP64_MFMA_PEAK_TFS,
-                "unit": "TFLOP/s", "frac": gemm_tfs / FP64_MFMA_PEAK_TFS, "traffic": None}
+        roof = {"bound": "mfma", "kernel": "gram+rotate", "achieved": g["executed_tflops"], "peak": g["peak_tflops"],
+                "unit": "TFLOP/s", "frac": g["utilisation"], "traffic": None}
     else:
-        roof = {"bound": "hbm", "kernel": "hx_apply", "achieved": hx_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hx_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes_per_launch": hx_bytes_step / hx_launches,
+        hx_launches = m + 1
+        roof = {"bound": "hbm", "kernel": "hx_apply", "achieved": main_run["hx_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": main_run["hx_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": main_run["hx_bytes_step"] / hx_launches,
                 "avg_launch_ms": kern["hx_apply"]["avg_launch_ms"]}
 
     out = {
         "metric": "CheFSI iter/s",
-        "value": args.steps / elapsed,
+        "value": main_run["iter_per_s"],
         "unit": "iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == cs.FP64 else "f32+f64",
+        "dtype": "f64" if precision == "fp64" else "f32+bf16x3+f64",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: periodic {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} grid h={cfg.h[0]} bohr, "
-                               f"FD order {cfg.fd_order}, {cfg.n_atoms} atoms x {cfg.nproj_per_atom} KB projectors, "
+        "config": {"workload": f"{cfg.name}: {'x'.join(map(str, cfg.n))} grid h={cfg.h[0]} bohr, "
+                               f"bc {''.join('PD'[b] for b in cfg.bc)}, FD order {cfg.fd_order}, "
+                               f"{cfg.n_atoms} atoms x {cfg.nproj_per_atom} KB projectors, "
                                f"Ns={ns}, degree {m}, {precision}",
                    "grid": list(cfg.n), "ns": ns, "degree": m, "precision": precision, "nd": prob.nd},
         "roofline": roof,
-        "hx_gbs": hx_gbs,
-        "gemm_tflops": gemm_tfs,
+        "hx_gbs": main_run["hx_gbs"],
+        "gemm": g,
         "kernels": kern,
+        "solve_ms": main_run["solve_ms"],
     }
+    if other is not None:
+        out["compare"] = {
+            "precision": other["precision"], "iter_per_s": other["iter_per_s"], "ms_per_step": other["ms_per_step"],
+            "hx_gbs": other["hx_gbs"], "gemm": other["gemm"], "solve_ms": other["solve_ms"],
+            "kernels": {k: round(v["ms_per_step"], 3) for k, v in other["kernels"].items()},
+            "step_speedup_mixed_over_fp64": (other["iter_per_s"] / main_run["iter_per_s"] if precision == "fp64"
+                                             else main_run["iter_per_s"] / other["iter_per_s"]),
+        }
+        if "refine_ms" in other:
+            out["compare"]["refine_ms"] = other["refine_ms"]
+    if "refine_ms" in main_run:
+        out["refine_ms"] = main_run["refine_ms"]
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(prob, cfg, args.cpu_columns)

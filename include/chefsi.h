@@ -122,6 +122,11 @@ void chefsi_destroy(chefsi_handle_t* h);
  * (1 <= ns <= max_ns).  Writes *bytes; used for admission by memory. */
 int chefsi_workspace_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes);
 
+/* Device bytes the handle itself holds (Veff, projectors and their index
+ * tables, copied by chefsi_create); with the orbital block and
+ * chefsi_workspace_bytes() this is a request's whole device footprint. */
+int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
+
 /* Rigorous filter bounds for the first step (the paper names lam_hi the
  * largest eigenvalue of H and lam_cut the cutoff, Alg. 1, but does not say how
  * they are obtained; these are this library's reading):

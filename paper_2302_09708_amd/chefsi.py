@@ -35,7 +35,7 @@ PROF_HX, PROF_NL, PROF_GRAM, PROF_REDUCE, PROF_ROT, PROF_EIG, PROF_COPY = range(
 
 # every symbol include/chefsi.h declares
 EXPORTS = (
-    "chefsi_create", "chefsi_destroy", "chefsi_workspace_bytes", "chefsi_spectral_bounds",
+    "chefsi_create", "chefsi_destroy", "chefsi_workspace_bytes", "chefsi_handle_bytes", "chefsi_spectral_bounds",
     "chefsi_apply_h", "chefsi_filter", "chefsi_project", "chefsi_eigh", "chefsi_rotate",
     "chefsi_step", "chefsi_solve", "chefsi_refine_fp64", "chefsi_profile_enable",
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     lib.chefsi_destroy.argtypes = [vp]
     lib.chefsi_destroy.restype = None
     lib.chefsi_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    lib.chefsi_handle_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
@@ -181,6 +182,14 @@ class Handle:
         b = C.c_size_t()
         self._check(self._lib.chefsi_workspace_bytes(self.h, int(ns), C.byref(b)))
         return int(b.value)
+
+    def chefsi_handle_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_handle_bytes(self.h, C.byref(b)))
+        return int(b.value)
+
+    def device_bytes(self) -> int:
+        return self.chefsi_handle_bytes()
 
     def chefsi_spectral_bounds(self) -> Tuple[float, float, float]:
         lo, cut, hi = C.c_double(), C.c_double(), C.c_double()

@@ -76,6 +76,7 @@ struct EventPair {
 
 struct chefsi_handle {
   int device = 0;
+  size_t device_bytes = 0;  // sum of the handle's own device arrays
   int precision = CHEFSI_FP64;
   int n[3] = {0, 0, 0};
   double h[3] = {0, 0, 0};
@@ -587,9 +588,10 @@ int guarded(chefsi_handle* h, F&& f) {
 }
 
 template <typename T>
-T* upload(const T* src, size_t n) {
+T* upload(chefsi_handle* h, const T* src, size_t n) {
   T* d = nullptr;
   if (n == 0) return nullptr;
+  h->device_bytes += n * sizeof(T);
   if (hipMalloc(&d, n * sizeof(T)) != hipSuccess) throw Error{CHEFSI_ERR_OOM, "device allocation failed"};
   hipError_t e = hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -718,9 +720,9 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->py_override);
     check(h->hx_plan.ok, "no stencil tiling fits this grid");
 
-    h->veff64 = upload(h->veff_h.data(), nd);
+    h->veff64 = upload(h, h->veff_h.data(), nd);
     std::vector<float> v32(h->veff_h.begin(), h->veff_h.end());
-    h->veff32 = upload(v32.data(), nd);
+    h->veff32 = upload(h, v32.data(), nd);
 
     if (h->np_tot > 0) {
       const int na = h->n_atoms;
@@ -804,23 +806,23 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
         evals.assign(4, 0.0);
       }
       h->n_ent = (int)ecol.size();
-      h->rec_ptr = upload(rptr.data(), rptr.size());
-      h->rec = upload(recs.data(), recs.size());
-      h->ent_col = upload(ecol.data(), ecol.size());
-      h->ent_val64 = upload(evals.data(), evals.size());
+      h->rec_ptr = upload(h, rptr.data(), rptr.size());
+      h->rec = upload(h, recs.data(), recs.size());
+      h->ent_col = upload(h, ecol.data(), ecol.size());
+      h->ent_val64 = upload(h, evals.data(), evals.size());
       std::vector<float> ev32(evals.begin(), evals.end());
-      h->ent_val32 = upload(ev32.data(), ev32.size());
-      h->supp_off = upload(soff.data(), soff.size());
-      h->supp_idx = upload(h->supp_idx_h.data(), h->supp_idx_h.size());
-      h->chi_off = upload(coff.data(), coff.size());
-      h->nproj = upload(h->nproj_h.data(), h->nproj_h.size());
-      h->poff = upload(poff.data(), poff.size());
-      h->chi64 = upload(h->chi_h.data(), h->chi_h.size());
+      h->ent_val32 = upload(h, ev32.data(), ev32.size());
+      h->supp_off = upload(h, soff.data(), soff.size());
+      h->supp_idx = upload(h, h->supp_idx_h.data(), h->supp_idx_h.size());
+      h->chi_off = upload(h, coff.data(), coff.size());
+      h->nproj = upload(h, h->nproj_h.data(), h->nproj_h.size());
+      h->poff = upload(h, poff.data(), poff.size());
+      h->chi64 = upload(h, h->chi_h.data(), h->chi_h.size());
       std::vector<float> chi32(h->chi_h.begin(), h->chi_h.end());
-      h->chi32 = upload(chi32.data(), chi32.size());
-      h->gdv64 = upload(gdv.data(), gdv.size());
+      h->chi32 = upload(h, chi32.data(), chi32.size());
+      h->gdv64 = upload(h, gdv.data(), gdv.size());
       std::vector<float> gdv32(gdv.begin(), gdv.end());
-      h->gdv32 = upload(gdv32.data(), gdv32.size());
+      h->gdv32 = upload(h, gdv32.data(), gdv32.size());
     }
     *out = h;
     return CHEFSI_OK;
@@ -1047,6 +1049,12 @@ int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, 
     else
       refine_impl<float>(h, (float*)X, ns, degree, lam_lo, lam_cut, lam_hi, ws, L, s, ritz_host);
   });
+}
+
+int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  *bytes = h->device_bytes;
+  return CHEFSI_OK;
 }
 
 int chefsi_profile_enable(chefsi_handle_t* h, int32_t on) {
