@@ -72,6 +72,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with `python -m paper_2302_09708_amd.build`")
+    # PyTorch supplies device memory and streams; its HIP runtime must be the one in the
+    # process before the library's own dependency on libamdhip64 is resolved
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, sz, i32, dbl = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
     pd = C.POINTER(C.c_double)

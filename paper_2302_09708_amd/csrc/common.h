@@ -11,7 +11,8 @@ namespace chefsi {
 
 constexpr int kMaxRadius = 6;  // finite-difference order up to 12
 constexpr int kHxMaxThreads = 512;  // stencil threads per block (keeps 256 VGPRs per lane)
-constexpr int kHxMaxHalo = 4;       // halo values each stencil thread stages per plane
+constexpr int kHxMaxHalo = 4;            // halo values each stencil thread stages per plane
+constexpr size_t kHxMaxLds = 96 * 1024;  // dynamic LDS of one stencil block (gfx950: 160 KB per CU)
 
 // ---------------------------------------------------------------------------
 // hx_apply: fused  out = sa * ((H x) - sc * x) + sb * prev   for a block of vectors.

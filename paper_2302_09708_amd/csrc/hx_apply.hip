@@ -74,7 +74,9 @@ __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
+// AL: alpha of the block's orbital is staged in LDS (else read from HBM; only when the
+// projector count is too large for LDS)
+template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL, bool AL>
 __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int Q = 2 * R + 1;
@@ -102,18 +104,23 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   int* s_rp = reinterpret_cast<int*>(lds_raw);
   const int rp_slots = NL ? ((nzl + 1 + 3) & ~3) : 0;
   TC* s_alpha = reinterpret_cast<TC*>(s_rp + rp_slots);
-  const int al_slots = (NL && a.alpha_lds) ? ((a.np_tot + 1) & ~1) : 0;
+  const int al_slots = (NL && AL) ? ((a.np_tot + 1) & ~1) : 0;
   TC* s_nl = s_alpha + al_slots;
   TI* s_tile = reinterpret_cast<TI*>(s_nl + (NL ? 2 * plane_pts : 0));
 
   const TC* g_alpha = NL ? a.alpha + vec * a.np_tot : nullptr;
   if (NL) {
     for (int i = tid; i <= nzl; i += nthr) s_rp[i] = a.rec_ptr[tile * nz + z0 + i];
-    if (a.alpha_lds)
+    if (AL)
       for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
     for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
   }
-  const TC* alpha_src = a.alpha_lds ? s_alpha : g_alpha;
+  // typed address spaces: LDS reads stay ds_read and HBM reads stay global loads (a
+  // generic-address load would wait on every outstanding memory operation)
+  typedef __attribute__((address_space(3))) const TC lds_tc;
+  typedef __attribute__((address_space(1))) const TC glb_tc;
+  lds_tc* l_alpha = (lds_tc*)s_alpha;
+  glb_tc* h_alpha = (glb_tc*)g_alpha;
 
   const bool active = tid < nx * a.nyg;
   const int x = active ? tid % nx : 0;
@@ -203,6 +210,10 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
       ev[3] = __builtin_bit_cast(double, (unsigned long long)v1[2] | ((unsigned long long)v1[3] << 32));
     }
   };
+  auto alpha_at = [&](unsigned c) -> TC {
+    if constexpr (AL) return l_alpha[c];
+    else return h_alpha[c];
+  };
   // sum the projector term of local plane zl into its accumulator (first record prefetched)
   auto finish_plane = [&](int zl) {
     if (zl >= nzl) return;
@@ -210,15 +221,15 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
     const int rbeg = s_rp[zl], rend = s_rp[zl + 1];
     if (rbeg + tid < rend) {
       const int n = rc.x >> 16;
-      TC sum = ev[0] * alpha_src[rc.z & 0xffff] + ev[1] * alpha_src[(unsigned)rc.z >> 16] +
-               ev[2] * alpha_src[rc.w & 0xffff] + ev[3] * alpha_src[(unsigned)rc.w >> 16];
-      for (int e = rc.y + 4; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      TC sum = ev[0] * alpha_at(rc.z & 0xffff) + ev[1] * alpha_at((unsigned)rc.z >> 16) +
+               ev[2] * alpha_at(rc.w & 0xffff) + ev[3] * alpha_at((unsigned)rc.w >> 16);
+      for (int e = rc.y + 4; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
       acc[rc.x & 0xffff] = sum;
     }
     for (int r = rbeg + tid + nthr; r < rend; r += nthr) {  // more records than threads
       const int4 rr = a.rec[r];
       TC sum = TC(0);
-      for (int e = rr.y; e < rr.y + (rr.x >> 16); ++e) sum += a.ent_val[e] * alpha_src[a.ent_col[e]];
+      for (int e = rr.y; e < rr.y + (rr.x >> 16); ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
       acc[rr.x & 0xffff] = sum;
     }
   };
@@ -400,12 +411,15 @@ static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, in
     lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
     lds += 2 * (size_t)p.ty * a.nx * sizeof(TC);
     const size_t al = (size_t)((a.np_tot + 1) & ~1) * sizeof(TC);
-    a.alpha_lds = (lds + al <= 64 * 1024) ? 1 : 0;
+    a.alpha_lds = (lds + al <= kHxMaxLds) ? 1 : 0;
     if (a.alpha_lds) lds += al;
   }
-  if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
+  if (lds > kHxMaxLds) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(a.per_xcd * 8));
-  hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL>), grid, dim3(p.threads), lds, s, a);
+  if (NL && a.alpha_lds)
+    hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL, true>), grid, dim3(p.threads), lds, s, a);
+  else
+    hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL, false>), grid, dim3(p.threads), lds, s, a);
   return hipGetLastError();
 }
 
