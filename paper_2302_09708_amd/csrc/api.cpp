@@ -115,6 +115,7 @@ struct chefsi_handle {
   double* ent_val64 = nullptr;
   float* ent_val32 = nullptr;
   int n_ent = 0;
+  int wide_records = 0;  // 1 if a point carries more than four projector entries
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -296,6 +297,7 @@ HxArgs<TI, TC, TO> hx_args(const chefsi_handle* h, const TI* x, const TO* prev, 
   a.ent_col = h->ent_col;
   a.ent_val = nl_val;
   a.n_ent = h->n_ent;
+  a.wide = h->wide_records;
   a.alpha = alpha;
   a.np_tot = h->np_tot;
   a.nx = h->n[0];
@@ -716,6 +718,9 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
 
     HIP_TRY(hipGetDevice(&h->device));
     BLAS_TRY(rocblas_create_handle(&h->blas));
+    // the dense stage must give the same bits whatever else runs on the device (results of
+    // a request alone and among others are compared bit for bit): no atomics in rocBLAS
+    BLAS_TRY(rocblas_set_atomics_mode(h->blas, rocblas_atomics_not_allowed));
     if (const char* e = std::getenv("CHEFSI_HX_PY")) h->py_override = std::atoi(e);  // tiling only
     h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->py_override);
     check(h->hx_plan.ok, "no stencil tiling fits this grid");
@@ -797,6 +802,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
           ecol.push_back(0);
           evals.push_back(0.0);
         }
+        if (n > 4) h->wide_records = 1;
         auto col = [&](int k) { return k < n ? ecol[e0 + k] : 0; };
         recs[r] = make_int4(((y % hp.ty) * nx + x) | (n << 16), e0, col(0) | (col(1) << 16), col(2) | (col(3) << 16));
       }

@@ -35,6 +35,7 @@ struct HxArgs {
   const int* ent_col;   // alpha column of each entry (entries of a record padded to a multiple of 4)
   const TC* ent_val;    // chi value of each entry (zero in the padding)
   int n_ent;            // entries including padding
+  int wide;             // some record has more than four entries
   const TC* alpha;      // ns x np_tot, projector column fastest
   int np_tot;
   int alpha_lds;        // 1: stage the block's alpha row in LDS

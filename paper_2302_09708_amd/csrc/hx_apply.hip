@@ -184,30 +184,48 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
                                                 NL ? (int64_t)(a.rec_ptr[a.nty * nz]) * 16 : 0);
   const __amdgpu_buffer_rsrc_t rval = make_rsrc(NL ? (const void*)a.ent_val : (const void*)a.out,
                                                 NL ? (int64_t)a.n_ent * (int64_t)sizeof(TC) : 0);
+  const __amdgpu_buffer_rsrc_t rcol = make_rsrc(NL ? (const void*)a.ent_col : (const void*)a.out,
+                                                NL ? (int64_t)a.n_ent * 4 : 0);
   int4 rc = make_int4(0, 0, 0, 0), rn = make_int4(0, 0, 0, 0);
-  TC ev[4];
+  // ev: chi values of rc's first four entries; ev2/ec2: values and alpha columns of entries
+  // 5..8 (points inside two atoms' supports), fetched with them so neither waits
+  TC ev[4], ev2[4] = {TC(0), TC(0), TC(0), TC(0)};
+  unsigned ec2[4] = {0u, 0u, 0u, 0u};
+  const bool wide = NL && a.wide;
   auto load_record = [&](int zl) -> int4 {
     const int r = zl < nzl ? s_rp[zl] + tid : 0;
     const bool ok = zl < nzl && r < s_rp[zl + 1];
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(rrec, ok ? (unsigned)r * 16u : kOOB, 0, 0);
     return make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
   };
-  auto load_values = [&](const int4& r) {
-    const unsigned o = (r.x >> 16) > 0 ? (unsigned)r.y * (unsigned)sizeof(TC) : kOOB;
+  // four chi values at byte offset o (zeros for kOOB)
+  auto load4 = [&](unsigned o, TC (&dst)[4]) {
     if constexpr (sizeof(TC) == 4) {
       const auto v = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
       const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
-      ev[0] = __builtin_bit_cast(float, v0);
-      ev[1] = __builtin_bit_cast(float, v1);
-      ev[2] = __builtin_bit_cast(float, v2);
-      ev[3] = __builtin_bit_cast(float, v3);
+      dst[0] = __builtin_bit_cast(float, v0);
+      dst[1] = __builtin_bit_cast(float, v1);
+      dst[2] = __builtin_bit_cast(float, v2);
+      dst[3] = __builtin_bit_cast(float, v3);
     } else {
       const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
       const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rval, o == kOOB ? kOOB : o + 16u, 0, 0);
-      ev[0] = __builtin_bit_cast(double, (unsigned long long)v0[0] | ((unsigned long long)v0[1] << 32));
-      ev[1] = __builtin_bit_cast(double, (unsigned long long)v0[2] | ((unsigned long long)v0[3] << 32));
-      ev[2] = __builtin_bit_cast(double, (unsigned long long)v1[0] | ((unsigned long long)v1[1] << 32));
-      ev[3] = __builtin_bit_cast(double, (unsigned long long)v1[2] | ((unsigned long long)v1[3] << 32));
+      dst[0] = __builtin_bit_cast(double, (unsigned long long)v0[0] | ((unsigned long long)v0[1] << 32));
+      dst[1] = __builtin_bit_cast(double, (unsigned long long)v0[2] | ((unsigned long long)v0[3] << 32));
+      dst[2] = __builtin_bit_cast(double, (unsigned long long)v1[0] | ((unsigned long long)v1[1] << 32));
+      dst[3] = __builtin_bit_cast(double, (unsigned long long)v1[2] | ((unsigned long long)v1[3] << 32));
+    }
+  };
+  auto load_values = [&](const int4& r) {
+    const int n = r.x >> 16;
+    load4(n > 0 ? (unsigned)r.y * (unsigned)sizeof(TC) : kOOB, ev);
+    if (wide) {  // entries are padded to a multiple of four: entries 5..8 are one aligned group
+      load4(n > 4 ? (unsigned)(r.y + 4) * (unsigned)sizeof(TC) : kOOB, ev2);
+      const auto c = __builtin_amdgcn_raw_buffer_load_b128(rcol, n > 4 ? (unsigned)(r.y + 4) * 4u : kOOB, 0, 0);
+      ec2[0] = c[0];
+      ec2[1] = c[1];
+      ec2[2] = c[2];
+      ec2[3] = c[3];
     }
   };
   auto alpha_at = [&](unsigned c) -> TC {
@@ -223,7 +241,10 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
       const int n = rc.x >> 16;
       TC sum = ev[0] * alpha_at(rc.z & 0xffff) + ev[1] * alpha_at((unsigned)rc.z >> 16) +
                ev[2] * alpha_at(rc.w & 0xffff) + ev[3] * alpha_at((unsigned)rc.w >> 16);
-      for (int e = rc.y + 4; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
+      if (n > 4)  // padding entries carry chi = 0 and column 0
+        sum += ev2[0] * alpha_at(ec2[0]) + ev2[1] * alpha_at(ec2[1]) + ev2[2] * alpha_at(ec2[2]) +
+               ev2[3] * alpha_at(ec2[3]);
+      for (int e = rc.y + 8; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
       acc[rc.x & 0xffff] = sum;
     }
     for (int r = rbeg + tid + nthr; r < rend; r += nthr) {  // more records than threads

@@ -42,6 +42,7 @@ APPLY_CASES = [
     ((130, 12, 9), (0, 1, 0), 6, 2, 4, 4),    # rows wider than two waves
     ((45, 40, 50), (1, 0, 1), 2, 4, 4, 7),
     ((64, 64, 64), (0, 0, 1), 12, 6, 4, 3),
+    ((16, 15, 14), (0, 0, 0), 12, 12, 4, 5),  # up to 8 atoms' supports on one point (32 entries)
 ]
 
 
@@ -62,7 +63,10 @@ def test_apply_h_fp64(cs, case):
     assert np.abs(got - ref).max() <= 1e-13 * scale * 10
 
 
-@pytest.mark.parametrize("case", APPLY_CASES[:4], ids=[str(c[0]) for c in APPLY_CASES[:4]])
+FP32_CASES = APPLY_CASES[:4] + APPLY_CASES[-1:]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[str(c[0]) for c in FP32_CASES])
 def test_apply_h_fp32_mixed_handle(cs, case):
     n, bc, order, na, npa, ns = case
     prob = inputs.small_problem(n=n, h=(0.3, 0.27, 0.33), bc=bc, fd_order=order, n_atoms=na,
