@@ -157,8 +157,11 @@ int chefsi_project(chefsi_handle_t* h, const void* X, int32_t ns, double* Hs, do
 /* Subspace diagonalization (Alg. 1; Sec. 2.3): solve Hs Z = Ms Z D in FP64 on
  * the device.  Hs and Ms (device, ns x ns, ld ns, symmetric; upper triangles
  * read) are overwritten: Hs by Z (Z^T Ms Z = I, columns ordered by ascending
- * D), Ms by its Cholesky factor.  D (device, ns doubles) gets the eigenvalues
- * in ascending order.  CHEFSI_ERR_NOT_POSDEF if Ms is not positive definite. */
+ * D), Ms by the Cholesky factor of S Ms S, where S = diag(Ms_ii^-1/2) scales the
+ * pencil before the factorization (it leaves D unchanged and keeps the
+ * Cholesky usable when the filtered columns differ widely in norm).  D
+ * (device, ns doubles) gets the eigenvalues in ascending order.
+ * CHEFSI_ERR_NOT_POSDEF if Ms is not positive definite. */
 int chefsi_eigh(chefsi_handle_t* h, double* Hs, double* Ms, double* D, int32_t ns,
                 void* ws, size_t ws_bytes, void* stream);
 

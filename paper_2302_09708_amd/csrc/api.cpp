@@ -134,7 +134,8 @@ struct chefsi_handle {
 namespace {
 
 struct WsLayout {
-  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, partial = 0, zsplit = 0, solver = 0, total = 0;
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, sc = 0, info = 0, partial = 0, zsplit = 0, solver = 0,
+         total = 0;
   size_t bufB_bytes = 0, solver_bytes = 0;
   GramPlan gram;
 };
@@ -194,6 +195,8 @@ WsLayout layout(chefsi_handle* h, int ns) {
   L.d = off;
   off += align256((size_t)ns * 8);
   L.e = off;
+  off += align256((size_t)ns * 8);
+  L.sc = off;
   off += align256((size_t)ns * 8);
   L.info = off;
   off += 256;
@@ -439,9 +442,10 @@ void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayou
 }
 
 // Hs Z = Ms Z D in FP64 on the device (Alg. 1, Diagonalization; Sec. 2.3), as the standard
-// reduction of a symmetric-definite pencil: Ms = U^T U (Cholesky), C = U^-T Hs U^-1,
-// C = W D W^T (divide and conquer), Z = U^-1 W.  Z overwrites Hs, U overwrites Ms.
-// info[0] receives the Cholesky status, info[1] the eigensolver status.
+// reduction of a symmetric-definite pencil after a diagonal scaling S (S_ii = Ms_ii^-1/2):
+// S Ms S = U^T U (Cholesky), C = U^-T S Hs S U^-1, C = W D W^T (divide and conquer),
+// Z = S U^-1 W.  Z overwrites Hs, U overwrites Ms.  info[0] receives the Cholesky
+// status, info[1] the eigensolver status.
 void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
                hipStream_t s) {
   ProfScope ps(h, P_EIG, s);
@@ -449,6 +453,8 @@ void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, cons
   BLAS_TRY(rocblas_set_stream(h->blas, s));
   BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
   rocblas_int* info = at<rocblas_int>(ws, L.info);
+  double* sc = at<double>(ws, L.sc);
+  HIP_TRY(launch_pencil_scale(Hs, Ms, sc, ns, s));
   BLAS_TRY(rocsolver_dpotrf(h->blas, rocblas_fill_upper, ns, Ms, ns, info));
   BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
                          rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
@@ -458,6 +464,7 @@ void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, cons
                             at<double>(ws, L.e), info + 1));
   BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                          rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
+  HIP_TRY(launch_row_scale(Hs, sc, ns, s));
   ps.done();
 }
 

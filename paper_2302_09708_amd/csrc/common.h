@@ -121,6 +121,11 @@ hipError_t launch_gram_f64(const TA* A, const TB* B, int64_t nd, int ns, const G
 
 hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, double* C, hipStream_t s);
 
+// Diagonal scaling of the pencil (Hs, Ms) by sc_i = Ms_ii^-1/2 (sc: ns doubles, written),
+// and the matching back-transformation Z(i, j) <- sc_i Z(i, j).
+hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipStream_t s);
+hipError_t launch_row_scale(double* Z, const double* sc, int ns, hipStream_t s);
+
 template <typename TX, typename TO>
 hipError_t launch_rotate_f64(const TX* X, const double* Z, TO* O, int64_t nd, int ns, hipStream_t s);
 

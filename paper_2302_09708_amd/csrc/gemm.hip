@@ -191,6 +191,48 @@ hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, 
   return hipGetLastError();
 }
 
+// Symmetric diagonal scaling of the pencil before its Cholesky: s_i = Ms_ii^-1/2 (or 1
+// when Ms_ii is not positive, so the Cholesky reports the failure), Hs <- S Hs S,
+// Ms <- S Ms S.  The eigenvalues do not change; the eigenvectors of the scaled pencil
+// map back as Z = S Z'.  It removes the spread of column norms that the filter leaves
+// in the block, which otherwise limits the Cholesky in reduced precision.
+__global__ void pencil_scale_kernel(double* __restrict__ Hs, double* __restrict__ Ms, const double* __restrict__ sc,
+                                    int ns) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ns * ns) return;
+  const int i = (int)(e % ns), j = (int)(e / ns);
+  const double f = sc[i] * sc[j];
+  Hs[e] *= f;
+  Ms[e] *= f;
+}
+
+__global__ void pencil_diag_kernel(const double* __restrict__ Ms, double* __restrict__ sc, int ns) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const double d = Ms[(int64_t)i * ns + i];
+  sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+}
+
+// Z(i, j) <- sc_i Z(i, j)
+__global__ void row_scale_kernel(double* __restrict__ Z, const double* __restrict__ sc, int ns) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ns * ns) return;
+  Z[e] *= sc[(int)(e % ns)];
+}
+
+hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(pencil_diag_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, Ms, sc, ns);
+  const int64_t n2 = (int64_t)ns * ns;
+  hipLaunchKernelGGL(pencil_scale_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, Hs, Ms, sc, ns);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_scale(double* Z, const double* sc, int ns, hipStream_t s) {
+  const int64_t n2 = (int64_t)ns * ns;
+  hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, Z, sc, ns);
+  return hipGetLastError();
+}
+
 // O = X Z computed as (Z^T X^T)^T so that the MFMA result rows run along the grid
 // index m: each store writes 16 consecutive m (128 bytes) of 4 columns.
 template <typename TX, typename TO>

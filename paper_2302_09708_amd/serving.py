@@ -46,6 +46,7 @@ class Result:
     finished: float
     footprint: int
     slot: int
+    error: Optional[str] = None   # set (and output None) when the solve failed
 
     @property
     def latency(self) -> float:
@@ -69,11 +70,12 @@ def nearest_rank(values, p: float) -> float:
 
 def summarize(results: List[Result]) -> Dict[str, float]:
     lat = [r.latency for r in results]
+    failed = sum(1 for r in results if r.error is not None)
     t_first = min(r.arrival for r in results)
     t_last = max(r.finished for r in results)
     return {"requests": len(results), "p50_s": nearest_rank(lat, 50), "p99_s": nearest_rank(lat, 99),
             "mean_s": float(np.mean(lat)), "makespan_s": t_last - t_first,
-            "solves_per_s": len(results) / (t_last - t_first)}
+            "solves_per_s": (len(results) - failed) / (t_last - t_first), "failed": failed}
 
 
 class AdmissionError(RuntimeError):
@@ -86,16 +88,19 @@ class Scheduler:
     open_fn(request) -> (state, footprint_bytes) runs at arrival on the scheduling
     thread; run_fn(state, slot) -> output runs on the slot's worker thread;
     close_fn(state) releases what open_fn acquired.  A request whose footprint
-    exceeds the whole budget is refused with AdmissionError."""
+    exceeds the whole budget is refused with AdmissionError.  With fail_fast the first
+    exception of a solve stops the loop and is raised; otherwise the request's Result
+    carries the error and the loop goes on."""
 
     def __init__(self, budget_bytes: int, slots: int, open_fn: Callable, run_fn: Callable,
-                 close_fn: Optional[Callable] = None, clock=time.perf_counter):
+                 close_fn: Optional[Callable] = None, clock=time.perf_counter, fail_fast: bool = True):
         if slots < 1 or budget_bytes <= 0:
             raise ValueError("need at least one slot and a positive budget")
         self.budget = int(budget_bytes)
         self.slots = slots
         self.open_fn, self.run_fn, self.close_fn = open_fn, run_fn, close_fn
         self.clock = clock
+        self.fail_fast = fail_fast
         self.peak_bytes = 0
         self.peak_active = 0
 
@@ -116,9 +121,12 @@ class Scheduler:
                 out = self.run_fn(state, slot)
                 t_end = self.clock() - t0
                 res = Result(req.rid, out, t_arr, t_adm, t_end, fp, slot)
-            except BaseException as e:  # surfaced to the caller after the drain
-                res = None
-                errors.append(e)
+            except BaseException as e:
+                if self.fail_fast:  # surfaced to the caller after the drain
+                    res = None
+                    errors.append(e)
+                else:
+                    res = Result(req.rid, None, t_arr, t_adm, self.clock() - t0, fp, slot, error=repr(e))
             finally:
                 if self.close_fn is not None:
                     try:

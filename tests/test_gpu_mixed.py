@@ -178,3 +178,31 @@ def test_refine_degree0_is_fp64_rayleigh_ritz(cs):
         x = x * np.sign(np.sum(x * ref, axis=0))[None, :]  # eigenvectors up to sign
         tol = 1e-6 if prec == cs.MIXED else 1e-11
         assert np.abs(x - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec_name", ["mixed", "fp64"])
+def test_projection_and_eigh_with_widely_scaled_columns(cs, prec_name):
+    """Column norms from 1e-4 to 1e4 (cond(Ms) ~ 1e16): the diagonally scaled Cholesky still
+    factors the pencil, and the Ritz values do not depend on the column scaling."""
+    prec = cs.MIXED if prec_name == "mixed" else cs.FP64
+    dt = "float32" if prec == cs.MIXED else "float64"
+    prob = inputs.small_problem(n=(14, 13, 12), n_atoms=3, nproj_per_atom=4, seed=3)
+    ns = 48
+    rng = np.random.default_rng(4)
+    base = rng.standard_normal((prob.nd, ns))
+    scale = 10.0 ** np.linspace(-4, 4, ns)
+    X = base * scale[None, :]
+    if prec == cs.MIXED:
+        X = _f32(X)
+    hs, ms = oc.project(prob, X / scale[None, :])  # same subspace, unit-scale columns
+    d_ref, _ = oc.diagonalize(hs, ms)
+    h, ws = _handle(cs, prob, ns, prec)
+    Hs = torch.zeros(ns, ns, dtype=torch.float64, device="cuda")
+    Ms = torch.zeros_like(Hs)
+    h.chefsi_project(dev(X, dt), ns, Hs, Ms, ws)
+    D = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    h.chefsi_eigh(Hs, Ms, D, ns, ws)
+    d = D.cpu().numpy()
+    tol = 2e-4 if prec == cs.MIXED else 1e-8
+    print(f"{prec_name}: max |dRitz| / max |Ritz| = {np.abs(d - d_ref).max() / np.abs(d_ref).max():.2e}", flush=True)
+    assert np.abs(d - d_ref).max() <= tol * np.abs(d_ref).max()

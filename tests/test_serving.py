@@ -120,6 +120,24 @@ def test_worker_error_propagates_and_releases():
     assert 1 in f.closed
 
 
+def test_failed_solve_is_reported_when_not_fail_fast():
+    f = Fake()
+
+    def bad_run(req, slot):
+        if req.rid == 1:
+            raise RuntimeError("solve failed")
+        return f.run(req, slot)
+
+    s = Scheduler(budget_bytes=100, slots=2, open_fn=f.open, run_fn=bad_run, close_fn=f.close, fail_fast=False)
+    res = s.run([_req(0, 0.0, 1, 0.02), _req(1, 0.0, 1, 0.02), _req(2, 0.01, 1, 0.02)])
+    assert [r.rid for r in res] == [0, 1, 2]
+    assert res[1].error is not None and "solve failed" in res[1].error and res[1].output is None
+    assert res[0].error is None and res[2].output == 20
+    st = summarize(res)
+    assert st["failed"] == 1 and st["requests"] == 3
+    assert sorted(f.closed) == [0, 1, 2]
+
+
 def test_bad_configuration():
     f = Fake()
     with pytest.raises(ValueError):
