@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TFS = 2500.0    # MI355X dense BF16 matrix
-KERNELS = ["hx_apply", "nl_project", "gram", "gram_reduce", "rotate", "dense_eig", "copy"]
+KERNELS = ["hx_apply", "nl_project", "gram", "gram_reduce", "rotate", "dense_eig", "copy", "fp64_fallback_steps"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hx_apply_cfg2_fp64_traffic.txt")
 
 

@@ -205,7 +205,10 @@ int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree,
 /* Per-kernel timing with HIP events recorded on the call's stream around every
  * launch of the named kernel (off by default; enabling it adds event records
  * but changes no result).  kernel ids: 0 hx_apply, 1 nl_project, 2 gram,
- * 3 gram_reduce, 4 rotate, 5 dense eigensolve (whole FP64 stage), 6 copy.
+ * 3 gram_reduce, 4 rotate, 5 dense eigensolve (whole FP64 stage), 6 copy,
+ * 7 mixed steps redone in FP64 (count only, kept whether or not timing is on:
+ * a mixed step whose scaled overlap matrix has a Cholesky pivot below 1e-4, or
+ * no Cholesky, forms its projection and rotation with FP64 arithmetic instead).
  * chefsi_profile_read synchronizes on the recorded events and returns the
  * summed milliseconds and launch count since the last reset. */
 int chefsi_profile_enable(chefsi_handle_t* h, int32_t on);

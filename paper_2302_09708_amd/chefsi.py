@@ -31,7 +31,7 @@ ERR_NONFINITE = 6
 ERR_SOLVER = 7
 ERR_OOM = 8
 
-PROF_HX, PROF_NL, PROF_GRAM, PROF_REDUCE, PROF_ROT, PROF_EIG, PROF_COPY = range(7)
+PROF_HX, PROF_NL, PROF_GRAM, PROF_REDUCE, PROF_ROT, PROF_EIG, PROF_COPY, PROF_FALLBACK = range(8)
 
 # every symbol include/chefsi.h declares
 EXPORTS = (

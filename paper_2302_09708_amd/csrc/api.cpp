@@ -23,8 +23,15 @@ using namespace chefsi;
 
 namespace {
 
-constexpr int kNumProf = 7;
-enum ProfId { P_HX = 0, P_NL = 1, P_GRAM = 2, P_REDUCE = 3, P_ROT = 4, P_EIG = 5, P_COPY = 6 };
+constexpr int kNumProf = 8;
+// P_FALLBACK counts mixed steps whose projection and rotation were redone in FP64 (no time)
+enum ProfId { P_HX = 0, P_NL = 1, P_GRAM = 2, P_REDUCE = 3, P_ROT = 4, P_EIG = 5, P_COPY = 6, P_FALLBACK = 7 };
+
+// A mixed step whose scaled overlap matrix has a Cholesky pivot below this (relative to its
+// unit diagonal, i.e. cond(S Ms S) beyond ~1e4) redoes projection and rotation in FP64:
+// the split-bf16 products (~1e-5 relative) cannot resolve the weakest filtered directions,
+// and the rotation would amplify their error by the inverse pivot.
+constexpr double kMixedMinPivot = 1e-4;
 
 struct Error {
   int status;
@@ -446,16 +453,27 @@ void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayou
 // S Ms S = U^T U (Cholesky), C = U^-T S Hs S U^-1, C = W D W^T (divide and conquer),
 // Z = S U^-1 W.  Z overwrites Hs, U overwrites Ms.  info[0] receives the Cholesky
 // status, info[1] the eigensolver status.
-void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
-               hipStream_t s) {
+// First half: scaling and Cholesky (info[0]); second half: reduction, eigensolve,
+// back substitution and back scaling (info[1]).
+void dense_factor(chefsi_handle* h, double* Hs, double* Ms, int ns, const WsLayout& L, void* ws, hipStream_t s) {
   ProfScope ps(h, P_EIG, s);
-  const double one = 1.0;
   BLAS_TRY(rocblas_set_stream(h->blas, s));
   BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
   rocblas_int* info = at<rocblas_int>(ws, L.info);
   double* sc = at<double>(ws, L.sc);
   HIP_TRY(launch_pencil_scale(Hs, Ms, sc, ns, s));
   BLAS_TRY(rocsolver_dpotrf(h->blas, rocblas_fill_upper, ns, Ms, ns, info));
+  ps.done();
+}
+
+void dense_solve(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
+                 hipStream_t s) {
+  ProfScope ps(h, P_EIG, s);
+  const double one = 1.0;
+  BLAS_TRY(rocblas_set_stream(h->blas, s));
+  BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+  rocblas_int* info = at<rocblas_int>(ws, L.info);
+  double* sc = at<double>(ws, L.sc);
   BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
                          rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
   BLAS_TRY(rocblas_dtrsm(h->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
@@ -466,6 +484,30 @@ void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, cons
                          rocblas_diagonal_non_unit, ns, ns, &one, Ms, ns, Hs, ns));
   HIP_TRY(launch_row_scale(Hs, sc, ns, s));
   ps.done();
+}
+
+void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, const WsLayout& L, void* ws,
+               hipStream_t s) {
+  dense_factor(h, Hs, Ms, ns, L, ws, s);
+  dense_solve(h, Hs, Ms, D, ns, L, ws, s);
+}
+
+// After dense_factor: true when the Cholesky failed or its smallest pivot U_ii^2 of the
+// scaled overlap matrix is below kMixedMinPivot (host round trip; the diagonal of U goes
+// through the eigensolver's scratch E, which is free until dense_solve).
+bool factor_is_weak(chefsi_handle* h, const double* U, int ns, const WsLayout& L, void* ws, hipStream_t s) {
+  double* diag = at<double>(ws, L.e);
+  HIP_TRY(hipMemcpy2DAsync(diag, sizeof(double), U, (size_t)(ns + 1) * sizeof(double), sizeof(double), ns,
+                           hipMemcpyDeviceToDevice, s));
+  std::vector<double> d(ns);
+  rocblas_int info = 0;
+  HIP_TRY(hipMemcpyAsync(d.data(), diag, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (info > 0) return true;
+  double mn = 1.0;
+  for (double v : d) mn = std::min(mn, v * v);
+  return !(mn >= kMixedMinPivot);
 }
 
 // Map the two dense-stage status words to a status (the Cholesky failure is reported as
@@ -540,9 +582,18 @@ void step_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, dou
   T* Xf = run_filter<T>(h, A, B, ns, m, lo, cut, hi, alpha, s);
   T* Yf = Xf == A ? B : A;
   apply_fused<T, T, T>(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
-  gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s, step_gemm(h));
-  dense_eig(h, Hs, Ms, D, ns, L, ws, s);
-  rotate_into<T>(h, Xf, Hs, Yf, ns, s, step_gemm(h), ws, L);  // Y~ is dead: X = X~ Z~ goes there
+  Gemm g = step_gemm(h);
+  gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s, g);
+  dense_factor(h, Hs, Ms, ns, L, ws, s);
+  if (g == Gemm::BF16X3 && factor_is_weak(h, Ms, ns, L, ws, s)) {
+    // the filtered block is too ill-conditioned for split-bf16 products: FP64 this step
+    g = Gemm::F64;
+    h->prof_n[P_FALLBACK] += 1;
+    gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s, g);
+    dense_factor(h, Hs, Ms, ns, L, ws, s);
+  }
+  dense_solve(h, Hs, Ms, D, ns, L, ws, s);
+  rotate_into<T>(h, Xf, Hs, Yf, ns, s, g, ws, L);  // Y~ is dead: X = X~ Z~ goes there
   if (Yf != X) copy_block<T>(h, X, Yf, ns, s);
   ritz_to_host(h, D, ns, ritz_host, ws, L, s);
 }

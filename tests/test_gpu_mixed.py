@@ -206,3 +206,26 @@ def test_projection_and_eigh_with_widely_scaled_columns(cs, prec_name):
     tol = 2e-4 if prec == cs.MIXED else 1e-8
     print(f"{prec_name}: max |dRitz| / max |Ritz| = {np.abs(d - d_ref).max() / np.abs(d_ref).max():.2e}", flush=True)
     assert np.abs(d - d_ref).max() <= tol * np.abs(d_ref).max()
+
+
+@pytest.mark.parametrize("k", [241, 93])
+def test_mixed_falls_back_to_fp64_on_ill_conditioned_blocks(cs, k):
+    """Small grids carrying many orbitals and deep wells (serving requests 241: Cholesky of the
+    split-bf16 overlap fails; 93: its Ritz values overshoot the spectral bound): the mixed path
+    redoes those steps in FP64 and ends within the mixed bar of the FP64 path."""
+    prob, ns, degree, seed = inputs.serving_request(k)
+    x0 = inputs.initial_block(prob.nd, ns, seed)
+    out = {}
+    for prec, dt in ((cs.FP64, "float64"), (cs.MIXED, "float32")):
+        h, ws = _handle(cs, prob, ns, prec)
+        h.chefsi_profile_reset()
+        Xd = torch.from_numpy(x0).to(device="cuda", dtype=getattr(torch, dt))
+        d, _, _ = h.solve(Xd, ns, degree, 10, ws)
+        out[prec] = (d, h.chefsi_profile_read(cs.PROF_FALLBACK)[1])
+    d64, dmx = out[cs.FP64][0], out[cs.MIXED][0]
+    kchk = oc.gap_index(d64, int(ns / 1.2))
+    err = np.abs(dmx[:kchk] - d64[:kchk]).max()
+    print(f"request {k}: N={prob.n[0]} ns={ns} fallback steps={out[cs.MIXED][1]} N_chk={kchk} "
+          f"max|dRitz| vs FP64 = {err:.2e}", flush=True)
+    assert out[cs.MIXED][1] >= 1
+    assert err <= 1e-5
