@@ -115,14 +115,19 @@ struct chefsi_handle {
   double* gdv64 = nullptr;
   float* gdv32 = nullptr;
   // projector entries grouped by (y tile, z plane) of the stencil tiling: one record per touched point
-  HxPlan hx_plan;  // tiling for ns = 1 (only the z chunking depends on ns)
-  int* rec_ptr = nullptr;
-  int4* rec = nullptr;
+  HxPlan hx_plan;  // tiling for ns = 1 (checked at create; the z chunking depends on ns)
+  int4* rec = nullptr;           // scatter records (points with more than four entries)
+  int* hx_rec_ptr = nullptr;     // stencil-pass records (points with at most four entries)
+  HxRec<double>* hx_rec64 = nullptr;
+  HxRec<float>* hx_rec32 = nullptr;
   int* ent_col = nullptr;
   double* ent_val64 = nullptr;
   float* ent_val32 = nullptr;
-  int n_ent = 0;
-  int wide_records = 0;  // 1 if a point carries more than four projector entries
+  // pinned host staging for the small device-to-host reads of every step (Ritz values,
+  // dense-stage status, Cholesky pivots): max_ns doubles + 16 status words
+  double* pinned = nullptr;
+  int n_pts = 0;     // scatter records
+  int n_hxrec = 0;   // stencil-pass records
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -147,9 +152,11 @@ struct WsLayout {
   GramPlan gram;
 };
 
+// status words in the pinned staging buffer, after max_ns doubles
+rocblas_int* pinned_info(chefsi_handle* h) { return reinterpret_cast<rocblas_int*>(h->pinned + h->max_ns); }
+
 size_t elem_bytes(const chefsi_handle* h) { return h->precision == CHEFSI_FP64 ? 8 : 4; }
 
-bool plane_pts_ok(const chefsi_handle* h) { return (int64_t)h->hx_plan.ty * h->n[0] < 65536; }
 
 // Device workspace of the FP64 dense stage (Cholesky, two triangular solves for the
 // reduced matrix, symmetric eigensolve, back substitution); the calls run in sequence,
@@ -296,18 +303,17 @@ void check_bounds(double lo, double cut, double hi) {
 // ---- kernel wrappers -------------------------------------------------------
 template <typename TI, typename TC, typename TO>
 HxArgs<TI, TC, TO> hx_args(const chefsi_handle* h, const TI* x, const TO* prev, TO* out, const TC* veff,
-                           const TC* nl_val, const TC* alpha) {
+                           const TC* alpha) {
   HxArgs<TI, TC, TO> a{};
   a.x = x;
   a.prev = prev;
   a.out = out;
   a.veff = veff;
-  a.rec_ptr = h->np_tot > 0 ? h->rec_ptr : nullptr;
-  a.rec = h->rec;
-  a.ent_col = h->ent_col;
-  a.ent_val = nl_val;
-  a.n_ent = h->n_ent;
-  a.wide = h->wide_records;
+  a.rec_ptr = h->n_hxrec > 0 ? h->hx_rec_ptr : nullptr;
+  if constexpr (sizeof(TC) == 8)
+    a.rec = h->hx_rec64;
+  else
+    a.rec = h->hx_rec32;
   a.alpha = alpha;
   a.np_tot = h->np_tot;
   a.nx = h->n[0];
@@ -352,6 +358,8 @@ NlArgs<TI, TC> nl_args(const chefsi_handle* h, const TI* y, int ns, const TC* ch
 }
 
 // out = sa (H x - sc x) + sb prev, with the projector gather for x first.
+// out = sa ((H x) - sc x) + sb prev: projector gather (alpha), the stencil + Veff +
+// Chebyshev pass, then the projector scatter onto the support points.
 template <typename TI, typename TC, typename TO>
 void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns, double sa, double sc, double sb,
                  TC* alpha, hipStream_t s) {
@@ -375,15 +383,34 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
     HIP_TRY((launch_nl_project<TI, TC>(nl_args<TI, TC>(h, x, ns, chi, gdv, alpha), s)));
     ps.done();
   }
-  auto a = hx_args<TI, TC, TO>(h, x, prev, out, veff, nlv, alpha);
+  auto a = hx_args<TI, TC, TO>(h, x, prev, out, veff, alpha);
   a.sa = TC(sa);
   a.sc = TC(sc);
   a.sb = TC(sb);
-  const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->py_override);
-  if (!p.ok || p.ty != h->hx_plan.ty) throw Error{CHEFSI_ERR_HIP, "stencil tiling differs from the one the projector records were built for"};
-  ProfScope ps(h, P_HX, s);
-  HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
-  ps.done();
+  {
+    ProfScope ps(h, P_HX, s);
+    const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->py_override);
+    if (!p.ok || p.ty != h->hx_plan.ty)
+      throw Error{CHEFSI_ERR_HIP, "stencil tiling differs from the one the projector records were built for"};
+    HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
+    ps.done();
+  }
+  if (h->n_pts > 0) {
+    NsArgs<TC, TO> n{};
+    n.out = out;
+    n.nd = h->nd;
+    n.ns = ns;
+    n.rec = h->rec;
+    n.n_pts = h->n_pts;
+    n.col = h->ent_col;
+    n.val = nlv;
+    n.alpha = alpha;
+    n.np_tot = h->np_tot;
+    n.sa = TC(sa);
+    ProfScope ps(h, P_NL, s);
+    HIP_TRY((launch_nl_scatter<TC, TO>(n, s)));
+    ps.done();
+  }
 }
 
 // Scaled Chebyshev filter (Alg. 1, Filtering).  Y_0 = X in buffer A; Y_{k+1} overwrites Y_{k-1}.
@@ -497,16 +524,15 @@ void dense_eig(chefsi_handle* h, double* Hs, double* Ms, double* D, int ns, cons
 // through the eigensolver's scratch E, which is free until dense_solve).
 bool factor_is_weak(chefsi_handle* h, const double* U, int ns, const WsLayout& L, void* ws, hipStream_t s) {
   double* diag = at<double>(ws, L.e);
-  HIP_TRY(hipMemcpy2DAsync(diag, sizeof(double), U, (size_t)(ns + 1) * sizeof(double), sizeof(double), ns,
-                           hipMemcpyDeviceToDevice, s));
-  std::vector<double> d(ns);
-  rocblas_int info = 0;
-  HIP_TRY(hipMemcpyAsync(d.data(), diag, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(launch_copy_diag(U, diag, ns, s));
+  double* d = h->pinned;
+  rocblas_int* info = pinned_info(h);
+  HIP_TRY(hipMemcpyAsync(d, diag, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (info > 0) return true;
+  if (info[0] > 0) return true;
   double mn = 1.0;
-  for (double v : d) mn = std::min(mn, v * v);
+  for (int i = 0; i < ns; ++i) mn = std::min(mn, d[i] * d[i]);
   return !(mn >= kMixedMinPivot);
 }
 
@@ -525,8 +551,8 @@ void raise_info(chefsi_handle* h, const rocblas_int* info, int ns) {
 }
 
 void check_info(chefsi_handle* h, void* ws, const WsLayout& L, int ns, hipStream_t s) {
-  rocblas_int info[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  rocblas_int* info = pinned_info(h);
+  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), 2 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   raise_info(h, info, ns);
 }
@@ -558,15 +584,15 @@ Gemm step_gemm(const chefsi_handle* h) { return h->precision == CHEFSI_MIXED ? G
 
 void ritz_to_host(chefsi_handle* h, const double* D, int ns, double* ritz_host, void* ws, const WsLayout& L,
                   hipStream_t s) {
-  rocblas_int info[2] = {0, 0};
-  std::vector<double> d(ns);
-  HIP_TRY(hipMemcpyAsync(d.data(), D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), sizeof(info), hipMemcpyDeviceToHost, s));
+  double* d = h->pinned;
+  rocblas_int* info = pinned_info(h);
+  HIP_TRY(hipMemcpyAsync(d, D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(info, at<rocblas_int>(ws, L.info), 2 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   raise_info(h, info, ns);
   for (int i = 0; i < ns; ++i)
     if (!std::isfinite(d[i])) throw Error{CHEFSI_ERR_NONFINITE, "non-finite Ritz value"};
-  if (ritz_host) std::memcpy(ritz_host, d.data(), (size_t)ns * 8);
+  if (ritz_host) std::memcpy(ritz_host, d, (size_t)ns * 8);
 }
 
 // One CheFSI step (Alg. 1) for element type T (double: FP64 handle, float: mixed handle).
@@ -663,7 +689,8 @@ T* upload(chefsi_handle* h, const T* src, size_t n) {
 
 void release(chefsi_handle* h) {
   void* ptrs[] = {h->veff64, h->veff32, h->supp_off, h->supp_idx, h->chi_off,  h->nproj,    h->poff,
-                  h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->rec_ptr,  h->rec,      h->ent_col,
+                  h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->rec,      h->ent_col,  h->hx_rec_ptr,
+                  h->hx_rec64, h->hx_rec32,
                   h->ent_val64,
                   h->ent_val32};
   for (void* p : ptrs)
@@ -673,6 +700,7 @@ void release(chefsi_handle* h) {
     (void)hipEventDestroy(p.e);
   }
   for (auto ev : h->ev_pool) (void)hipEventDestroy(ev);
+  if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->blas) rocblas_destroy_handle(h->blas);
 }
 
@@ -783,6 +811,10 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->py_override);
     check(h->hx_plan.ok, "no stencil tiling fits this grid");
 
+    if (hipHostMalloc((void**)&h->pinned, (size_t)max_ns * sizeof(double) + 64, hipHostMallocDefault) != hipSuccess) {
+      h->pinned = nullptr;
+      throw Error{CHEFSI_ERR_OOM, "pinned host allocation failed"};
+    }
     h->veff64 = upload(h, h->veff_h.data(), nd);
     std::vector<float> v32(h->veff_h.begin(), h->veff_h.end());
     h->veff32 = upload(h, v32.data(), nd);
@@ -823,35 +855,55 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
           }
         }
       }
-      // regroup by (y tile, z plane) of the stencil tiling: one record per touched point,
-      // its entries contiguous and in atom order
+      // points with at most four entries: one stencil-pass record each, grouped by
+      // (y tile, z plane) of the tiling (at most ty*nx per group <= PY * threads);
+      // points with more: one scatter record {point, first entry, entry count, 0} each,
+      // entries in atom order padded with zeros to a multiple of 4
       const HxPlan& hp = h->hx_plan;
       const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+      check(h->np_tot < 65536, "more than 65535 projectors");
+      const size_t lds_need = std::max(
+          hx_lds_bytes(hp, nx, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->np_tot, 8),
+          hx_lds_bytes(hp, nx, h->radius, 4, h->np_tot, 8));
+      check(lds_need <= kHxMaxLds, "too many projectors for the stencil pass (alpha row does not fit in LDS)");
       const int64_t nkeys = (int64_t)hp.nty * nz;
-      std::vector<int> rptr(nkeys + 1, 0);
       auto key_of = [&](int64_t i) {
         const int y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
         return (int64_t)(y / hp.ty) * nz + z;
       };
-      for (int64_t i = 0; i < nd; ++i)
-        if (cnt[i + 1] > cnt[i]) rptr[key_of(i) + 1] += 1;
+      std::vector<int> rptr(nkeys + 1, 0);
+      for (int64_t i = 0; i < nd; ++i) {
+        const int n = cnt[i + 1] - cnt[i];
+        if (n >= 1 && n <= 4) rptr[key_of(i) + 1] += 1;
+      }
       for (int64_t k = 0; k < nkeys; ++k) rptr[k + 1] += rptr[k];
       const int nrec = rptr[nkeys];
+      std::vector<HxRec<double>> r64(std::max(nrec, 1));
+      std::vector<HxRec<float>> r32(std::max(nrec, 1));
+      std::memset(r64.data(), 0, r64.size() * sizeof(HxRec<double>));
+      std::memset(r32.data(), 0, r32.size() * sizeof(HxRec<float>));
       std::vector<int> rfill(rptr.begin(), rptr.end() - 1);
-      std::vector<int> rec_pt(nrec);
-      for (int64_t i = 0; i < nd; ++i)
-        if (cnt[i + 1] > cnt[i]) rec_pt[rfill[key_of(i)]++] = (int)i;
-      // entries of each record padded with zeros to a multiple of 4 (one vector load each)
-      std::vector<int4> recs(std::max(nrec, 1), make_int4(0, 0, 0, 0));
+      std::vector<int4> recs;
       std::vector<int> ecol;
       std::vector<double> evals;
-      check(plane_pts_ok(h), "tile plane too large for 16-bit record indices");
-      check(h->np_tot < 65536, "more than 65535 projectors");
-      for (int r = 0; r < nrec; ++r) {
-        const int64_t i = rec_pt[r];
-        const int x = (int)(i % nx), y = (int)((i / nx) % ny);
+      for (int64_t i = 0; i < nd; ++i) {
         const int n = cnt[i + 1] - cnt[i];
-        const int e0 = (int)ecol.size();
+        if (n == 0) continue;
+        if (n <= 4) {
+          const int r = rfill[key_of(i)]++;
+          const int x = (int)(i % nx), y = (int)((i / nx) % ny);
+          int col[4] = {0, 0, 0, 0};
+          for (int k = 0; k < n; ++k) {
+            col[k] = eproj[cnt[i] + k];
+            r64[r].val[k] = eval[cnt[i] + k];
+            r32[r].val[k] = (float)eval[cnt[i] + k];
+          }
+          r64[r].lidx = r32[r].lidx = (y % hp.ty) * nx + x;
+          r64[r].c01 = r32[r].c01 = col[0] | (col[1] << 16);
+          r64[r].c23 = r32[r].c23 = col[2] | (col[3] << 16);
+          continue;
+        }
+        recs.push_back(make_int4((int)i, (int)ecol.size(), n, 0));
         for (int k = cnt[i]; k < cnt[i + 1]; ++k) {
           ecol.push_back(eproj[k]);
           evals.push_back(eval[k]);
@@ -860,22 +912,22 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
           ecol.push_back(0);
           evals.push_back(0.0);
         }
-        if (n > 4) h->wide_records = 1;
-        auto col = [&](int k) { return k < n ? ecol[e0 + k] : 0; };
-        recs[r] = make_int4(((y % hp.ty) * nx + x) | (n << 16), e0, col(0) | (col(1) << 16), col(2) | (col(3) << 16));
       }
       check(ecol.size() < ((size_t)1 << 31), "too many projector entries");
-      if (ecol.empty()) {
-        ecol.assign(4, 0);
-        evals.assign(4, 0.0);
+      h->n_hxrec = nrec;
+      if (nrec > 0) {
+        h->hx_rec_ptr = upload(h, rptr.data(), rptr.size());
+        h->hx_rec64 = upload(h, r64.data(), r64.size());
+        h->hx_rec32 = upload(h, r32.data(), r32.size());
       }
-      h->n_ent = (int)ecol.size();
-      h->rec_ptr = upload(h, rptr.data(), rptr.size());
-      h->rec = upload(h, recs.data(), recs.size());
-      h->ent_col = upload(h, ecol.data(), ecol.size());
-      h->ent_val64 = upload(h, evals.data(), evals.size());
-      std::vector<float> ev32(evals.begin(), evals.end());
-      h->ent_val32 = upload(h, ev32.data(), ev32.size());
+      h->n_pts = (int)recs.size();
+      if (!recs.empty()) {
+        h->rec = upload(h, recs.data(), recs.size());
+        h->ent_col = upload(h, ecol.data(), ecol.size());
+        h->ent_val64 = upload(h, evals.data(), evals.size());
+        std::vector<float> ev32(evals.begin(), evals.end());
+        h->ent_val32 = upload(h, ev32.data(), ev32.size());
+      }
       h->supp_off = upload(h, soff.data(), soff.size());
       h->supp_idx = upload(h, h->supp_idx_h.data(), h->supp_idx_h.size());
       h->chi_off = upload(h, coff.data(), coff.size());

@@ -15,30 +15,32 @@ constexpr int kHxMaxHalo = 4;            // halo values each stencil thread stag
 constexpr size_t kHxMaxLds = 96 * 1024;  // dynamic LDS of one stencil block (gfx950: 160 KB per CU)
 
 // ---------------------------------------------------------------------------
-// hx_apply: fused  out = sa * ((H x) - sc * x) + sb * prev   for a block of vectors.
-// H x = c0 x + sum_p cx[p](x[i+-p ex]) + cy.. + cz.. + veff x + (projector term).
-// The projector term at a point is sum over its entries of chi * alpha[v][column]; the
-// entries are grouped into per-(y tile, z plane) point records so that a block can
-// gather them for a whole plane ahead of time.
+// hx_apply: fused  out = sa * ((H_loc x) - sc * x) + sb * prev   for a block of vectors,
+// H_loc x = c0 x + sum_p cx[p](x[i+-p ex]) + cy.. + cz.. + veff x + (projector term of the
+// points whose record fits four entries; the rest of V_nl x is added by nl_scatter).
 // TI: element type of x; TC: arithmetic type; TO: element type of prev/out.
 // ---------------------------------------------------------------------------
+template <typename TC>
+struct alignas(16) HxRec {
+  int lidx;     // point inside the tile plane: ly * nx + x
+  int c01;      // alpha columns of entries 0 and 1 (16 bits each)
+  int c23;      // alpha columns of entries 2 and 3
+  int pad;
+  TC val[4];    // chi values of the (up to) four entries, zero past the last
+};
+
 template <typename TI, typename TC, typename TO>
 struct HxArgs {
   const TI* x;
   const TO* prev;  // may be null when sb == 0
   TO* out;
   const TC* veff;
-  // projector records (rec_ptr == null when there are no projectors)
-  const int* rec_ptr;   // nty * nz + 1: records of (tile t, plane z) are [rec_ptr[t*nz+z], rec_ptr[t*nz+z+1])
-  const int4* rec;      // {local point ly*nx+x | entry count << 16, first entry (a multiple of 4),
-                        //  col0 | col1 << 16, col2 | col3 << 16}: alpha columns of the first 4 entries
-  const int* ent_col;   // alpha column of each entry (entries of a record padded to a multiple of 4)
-  const TC* ent_val;    // chi value of each entry (zero in the padding)
-  int n_ent;            // entries including padding
-  int wide;             // some record has more than four entries
-  const TC* alpha;      // ns x np_tot, projector column fastest
+  // projector term of the points with at most four entries (the others go to nl_scatter):
+  // one record per point, grouped by (y tile, z plane); rec_ptr == null when there are none
+  const int* rec_ptr;      // nty * nz + 1: records of (tile t, plane z) are [rec_ptr[t*nz+z], rec_ptr[t*nz+z+1])
+  const HxRec<TC>* rec;
+  const TC* alpha;         // ns x np_tot, projector column fastest (staged in LDS per block)
   int np_tot;
-  int alpha_lds;        // 1: stage the block's alpha row in LDS
   int nx, ny, nz;
   int64_t nd;           // leading dimension of x, prev, out
   int per_x, per_y, per_z;  // 1 = periodic, 0 = Dirichlet
@@ -71,6 +73,9 @@ struct HxPlan {
 // Choose the tiling for one grid (deterministic in the shape only; ns only sets the z chunks).
 HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override);
 
+// Dynamic LDS of one stencil block; np_tot < 0: no projector records.
+size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes);
+
 template <typename TI, typename TC, typename TO>
 hipError_t launch_hx(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int radius, int ns, hipStream_t s);
 
@@ -99,6 +104,28 @@ template <typename TI, typename TC>
 hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// nl_scatter: out[v * nd + p] += sa * sum_{e in entries of p} val[e] * alpha[v * np_tot + col[e]]
+// for every support point p (one record per point: {p, first entry, entry count, 0},
+// entries padded to a multiple of four) and vector v.
+// ---------------------------------------------------------------------------
+template <typename TC, typename TO>
+struct NsArgs {
+  TO* out;
+  int64_t nd;
+  int ns;
+  const int4* rec;
+  int n_pts;
+  const int* col;
+  const TC* val;
+  const TC* alpha;
+  int np_tot;
+  TC sa;
+};
+
+template <typename TC, typename TO>
+hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Dense products on MFMA.
 // gram:   partial[split][tile] = A(:, I)^T B(:, J) over a K range, for upper tiles I <= J.
 // reduce: C(i, j) = C(j, i) = sum_split partial (i <= j), C is ns x ns, ld ns, FP64.
@@ -125,6 +152,8 @@ hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, 
 // and the matching back-transformation Z(i, j) <- sc_i Z(i, j).
 hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipStream_t s);
 hipError_t launch_row_scale(double* Z, const double* sc, int ns, hipStream_t s);
+// d[i] = A(i, i) for an ns x ns column-major matrix
+hipError_t launch_copy_diag(const double* A, double* d, int ns, hipStream_t s);
 
 template <typename TX, typename TO>
 hipError_t launch_rotate_f64(const TX* X, const double* Z, TO* O, int64_t nd, int ns, hipStream_t s);

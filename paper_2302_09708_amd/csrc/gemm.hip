@@ -227,6 +227,16 @@ hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipSt
   return hipGetLastError();
 }
 
+__global__ void copy_diag_kernel(const double* __restrict__ A, double* __restrict__ d, int ns) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) d[i] = A[(int64_t)i * ns + i];
+}
+
+hipError_t launch_copy_diag(const double* A, double* d, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(copy_diag_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, A, d, ns);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_scale(double* Z, const double* sc, int ns, hipStream_t s) {
   const int64_t n2 = (int64_t)ns * ns;
   hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, Z, sc, ns);

@@ -2,11 +2,19 @@
 //
 // Sec. 2.1 applies H in three parts: the finite-difference Laplacian stencil of
 // order n0 = 2r (3 n0 + 1 operations per output point), the pointwise Veff
-// product and the Kleinman-Bylander projectors.  Here the three are one pass
-// over HBM, and the Chebyshev three-term update of Alg. 1 (scaled form) is the
+// product and the Kleinman-Bylander projectors.  Here the stencil and Veff are one
+// pass over HBM, and the Chebyshev three-term update of Alg. 1 (scaled form) is the
 // epilogue, so one launch reads Y_k and Y_{k-1} once and writes Y_{k+1} once:
 //
-//   out[i] = sa * ((H y)[i] - sc * y[i]) + sb * prev[i]
+//   out[i] = sa * ((T + Veff) y - sc * y)[i] + sb * prev[i]
+//
+// Projector term: a point inside at most four projector entries (every point of the
+// workloads with isolated atoms, ~90 % of the touched points with overlapping ones)
+// is added in this pass from a 32/48-byte record holding its four alpha columns and
+// chi values; each thread owns at most PY records per plane (a tile plane has at most
+// PY * threads points), fetched one plane ahead with no dependent load and no inner
+// loop.  The block's alpha row sits in LDS.  Points with more entries are left to
+// nl_scatter, which adds theirs after this pass.
 //
 // Mapping on gfx950 (wave64, 160 KB LDS per CU, 8 XCDs with private L2):
 //   * one block = one orbital x one tile of whole x-rows (nx wide, ty = nyg*PY
@@ -22,11 +30,7 @@
 //     PY rows a thread owns.  The kernel is kept lean in registers: on this path
 //     occupancy hides memory latency better than deeper per-thread prefetch;
 //   * global reads are buffer loads: a Dirichlet ghost is an out-of-range offset,
-//     which returns zero without touching memory, so the loads need no branches;
-//   * projector term (NL): the block stages its orbital's gather coefficients alpha
-//     in LDS; the points of each tile plane that projectors touch are listed as
-//     records whose entries are fetched a plane ahead and summed into an LDS
-//     accumulator by one thread each (fixed order, no atomics: bitwise reproducible).
+//     which returns zero without touching memory, so the loads need no branches.
 #include "common.h"
 
 #include <algorithm>
@@ -74,9 +78,34 @@ __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-// AL: alpha of the block's orbital is staged in LDS (else read from HBM; only when the
-// projector count is too large for LDS)
-template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL, bool AL>
+// one projector record (zeros at kOOB): 32 bytes for FP32 values, 48 for FP64
+template <typename TC>
+__device__ __forceinline__ void load_rec(__amdgpu_buffer_rsrc_t r, unsigned off, int (&hdr)[3], TC (&v)[4]) {
+  const auto h = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const unsigned h0 = h[0], h1 = h[1], h2 = h[2];
+  hdr[0] = (int)h0;
+  hdr[1] = (int)h1;
+  hdr[2] = (int)h2;
+  const unsigned o1 = off == kOOB ? kOOB : off + 16u;
+  if constexpr (sizeof(TC) == 4) {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, 0, 0);
+    const unsigned w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+    v[0] = __builtin_bit_cast(float, w0);
+    v[1] = __builtin_bit_cast(float, w1);
+    v[2] = __builtin_bit_cast(float, w2);
+    v[3] = __builtin_bit_cast(float, w3);
+  } else {
+    const unsigned o2 = off == kOOB ? kOOB : off + 32u;
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, o2, 0, 0);
+    v[0] = __builtin_bit_cast(double, (unsigned long long)w[0] | ((unsigned long long)w[1] << 32));
+    v[1] = __builtin_bit_cast(double, (unsigned long long)w[2] | ((unsigned long long)w[3] << 32));
+    v[2] = __builtin_bit_cast(double, (unsigned long long)u[0] | ((unsigned long long)u[1] << 32));
+    v[3] = __builtin_bit_cast(double, (unsigned long long)u[2] | ((unsigned long long)u[3] << 32));
+  }
+}
+
+template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
 __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int Q = 2 * R + 1;
@@ -100,38 +129,45 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
 
   const int plane_pts = a.ty * nx;
   const int tile_elems = (a.ty + 2 * R) * nx;
-  // LDS: [record offsets of this chunk][alpha row][accumulator x2] (NL only) [tile plane x2]
+  // LDS: [record offsets of this chunk][alpha row][projector term x2] (NL only) [tile plane x2]
   int* s_rp = reinterpret_cast<int*>(lds_raw);
   const int rp_slots = NL ? ((nzl + 1 + 3) & ~3) : 0;
   TC* s_alpha = reinterpret_cast<TC*>(s_rp + rp_slots);
-  const int al_slots = (NL && AL) ? ((a.np_tot + 1) & ~1) : 0;
+  const int al_slots = NL ? ((a.np_tot + 1) & ~1) : 0;
   TC* s_nl = s_alpha + al_slots;
   TI* s_tile = reinterpret_cast<TI*>(s_nl + (NL ? 2 * plane_pts : 0));
-
-  const TC* g_alpha = NL ? a.alpha + vec * a.np_tot : nullptr;
-  if (NL) {
-    for (int i = tid; i <= nzl; i += nthr) s_rp[i] = a.rec_ptr[tile * nz + z0 + i];
-    if (AL)
-      for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
-    for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
-  }
-  // typed address spaces: LDS reads stay ds_read and HBM reads stay global loads (a
-  // generic-address load would wait on every outstanding memory operation)
-  typedef __attribute__((address_space(3))) const TC lds_tc;
-  typedef __attribute__((address_space(1))) const TC glb_tc;
+  typedef __attribute__((address_space(3))) const TC lds_tc;  // keeps the alpha reads ds_read
   lds_tc* l_alpha = (lds_tc*)s_alpha;
-  glb_tc* h_alpha = (glb_tc*)g_alpha;
 
   const bool active = tid < nx * a.nyg;
   const int x = active ? tid % nx : 0;
   const int ly0 = active ? (tid / nx) * PY : 0;
   const int nplane = nx * ny;
-  const bool has_prev = a.prev != nullptr;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x + vec * a.nd, a.nd * (int64_t)sizeof(TI));
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.veff, a.nd * (int64_t)sizeof(TC));
+  // with no previous iterate the resource has no records: its loads read zero
+  const bool has_prev = a.prev != nullptr;
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(has_prev ? (const void*)(a.prev + vec * a.nd) : (const void*)a.out,
                                               has_prev ? a.nd * (int64_t)sizeof(TO) : 0);
   TO* ov = a.out + vec * a.nd;
+  const __amdgpu_buffer_rsrc_t rrec =
+      make_rsrc(NL ? (const void*)a.rec : (const void*)a.out,
+                NL ? (int64_t)a.rec_ptr[a.nty * nz] * (int64_t)sizeof(HxRec<TC>) : 0);
+  // records of the plane being finished (hc, vc) and of the next one (hn, vn), PY per thread
+  int hc[PY][3], hn[PY][3];
+  TC vc[PY][4], vn[PY][4];
+  if (NL) {
+    const TC* g_alpha = a.alpha + vec * a.np_tot;
+    for (int i = tid; i <= nzl; i += nthr) s_rp[i] = a.rec_ptr[tile * nz + z0 + i];
+    for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
+    for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PY; ++r) {
+      const int ri = s_rp[0] + tid + r * nthr;
+      load_rec<TC>(rrec, ri < s_rp[1] ? (unsigned)ri * (unsigned)sizeof(HxRec<TC>) : kOOB, hc[r], vc[r]);
+    }
+  }
 
   int roff[PY];  // offset of the thread's rows inside a plane, -1 for a zero row
   bool valid[PY];
@@ -177,97 +213,16 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
     for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], ph));
   }
 
-  // projector records: rc is this thread's first record of the plane being prepared,
-  // rn the one of the plane after it (loaded a full iteration before it is needed);
-  // ev holds the chi values of rc's first four entries (one 16- or 32-byte load)
-  const __amdgpu_buffer_rsrc_t rrec = make_rsrc(NL ? (const void*)a.rec : (const void*)a.out,
-                                                NL ? (int64_t)(a.rec_ptr[a.nty * nz]) * 16 : 0);
-  const __amdgpu_buffer_rsrc_t rval = make_rsrc(NL ? (const void*)a.ent_val : (const void*)a.out,
-                                                NL ? (int64_t)a.n_ent * (int64_t)sizeof(TC) : 0);
-  const __amdgpu_buffer_rsrc_t rcol = make_rsrc(NL ? (const void*)a.ent_col : (const void*)a.out,
-                                                NL ? (int64_t)a.n_ent * 4 : 0);
-  int4 rc = make_int4(0, 0, 0, 0), rn = make_int4(0, 0, 0, 0);
-  // ev: chi values of rc's first four entries; ev2/ec2: values and alpha columns of entries
-  // 5..8 (points inside two atoms' supports), fetched with them so neither waits
-  TC ev[4], ev2[4] = {TC(0), TC(0), TC(0), TC(0)};
-  unsigned ec2[4] = {0u, 0u, 0u, 0u};
-  const bool wide = NL && a.wide;
-  auto load_record = [&](int zl) -> int4 {
-    const int r = zl < nzl ? s_rp[zl] + tid : 0;
-    const bool ok = zl < nzl && r < s_rp[zl + 1];
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rrec, ok ? (unsigned)r * 16u : kOOB, 0, 0);
-    return make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
-  };
-  // four chi values at byte offset o (zeros for kOOB)
-  auto load4 = [&](unsigned o, TC (&dst)[4]) {
-    if constexpr (sizeof(TC) == 4) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
-      const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
-      dst[0] = __builtin_bit_cast(float, v0);
-      dst[1] = __builtin_bit_cast(float, v1);
-      dst[2] = __builtin_bit_cast(float, v2);
-      dst[3] = __builtin_bit_cast(float, v3);
-    } else {
-      const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rval, o, 0, 0);
-      const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rval, o == kOOB ? kOOB : o + 16u, 0, 0);
-      dst[0] = __builtin_bit_cast(double, (unsigned long long)v0[0] | ((unsigned long long)v0[1] << 32));
-      dst[1] = __builtin_bit_cast(double, (unsigned long long)v0[2] | ((unsigned long long)v0[3] << 32));
-      dst[2] = __builtin_bit_cast(double, (unsigned long long)v1[0] | ((unsigned long long)v1[1] << 32));
-      dst[3] = __builtin_bit_cast(double, (unsigned long long)v1[2] | ((unsigned long long)v1[3] << 32));
-    }
-  };
-  auto load_values = [&](const int4& r) {
-    const int n = r.x >> 16;
-    load4(n > 0 ? (unsigned)r.y * (unsigned)sizeof(TC) : kOOB, ev);
-    if (wide) {  // entries are padded to a multiple of four: entries 5..8 are one aligned group
-      load4(n > 4 ? (unsigned)(r.y + 4) * (unsigned)sizeof(TC) : kOOB, ev2);
-      const auto c = __builtin_amdgcn_raw_buffer_load_b128(rcol, n > 4 ? (unsigned)(r.y + 4) * 4u : kOOB, 0, 0);
-      ec2[0] = c[0];
-      ec2[1] = c[1];
-      ec2[2] = c[2];
-      ec2[3] = c[3];
-    }
-  };
-  auto alpha_at = [&](unsigned c) -> TC {
-    if constexpr (AL) return l_alpha[c];
-    else return h_alpha[c];
-  };
-  // sum the projector term of local plane zl into its accumulator (first record prefetched)
-  auto finish_plane = [&](int zl) {
-    if (zl >= nzl) return;
-    TC* acc = s_nl + ((zl & 1) ? plane_pts : 0);
-    const int rbeg = s_rp[zl], rend = s_rp[zl + 1];
-    if (rbeg + tid < rend) {
-      const int n = rc.x >> 16;
-      TC sum = ev[0] * alpha_at(rc.z & 0xffff) + ev[1] * alpha_at((unsigned)rc.z >> 16) +
-               ev[2] * alpha_at(rc.w & 0xffff) + ev[3] * alpha_at((unsigned)rc.w >> 16);
-      if (n > 4)  // padding entries carry chi = 0 and column 0
-        sum += ev2[0] * alpha_at(ec2[0]) + ev2[1] * alpha_at(ec2[1]) + ev2[2] * alpha_at(ec2[2]) +
-               ev2[3] * alpha_at(ec2[3]);
-      for (int e = rc.y + 8; e < rc.y + n; ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
-      acc[rc.x & 0xffff] = sum;
-    }
-    for (int r = rbeg + tid + nthr; r < rend; r += nthr) {  // more records than threads
-      const int4 rr = a.rec[r];
-      TC sum = TC(0);
-      for (int e = rr.y; e < rr.y + (rr.x >> 16); ++e) sum += a.ent_val[e] * alpha_at(a.ent_col[e]);
-      acc[rr.x & 0xffff] = sum;
-    }
-  };
-  if (NL) {
-    __syncthreads();  // record offsets, alpha and the zeroed accumulators are visible
-    rc = load_record(0);
-    load_values(rc);
-    finish_plane(0);
-    rc = load_record(1);
-  }
-
   for (int zl = 0; zl < nzl; ++zl) {
     const int z = z0 + zl;
     TI* tl = s_tile + (zl & 1) * tile_elems;
-    if (NL) {
-      rn = load_record(zl + 2);
-      load_values(rc);  // first record of plane zl + 1
+    if (NL) {  // records of plane zl + 1
+#pragma unroll
+      for (int r = 0; r < PY; ++r) {
+        const int ri = zl + 1 < nzl ? s_rp[zl + 1] + tid + r * nthr : 0;
+        const bool ok = zl + 1 < nzl && ri < s_rp[zl + 2];
+        load_rec<TC>(rrec, ok ? (unsigned)ri * (unsigned)sizeof(HxRec<TC>) : kOOB, hn[r], vn[r]);
+      }
     }
     // Veff and previous iterate of this plane, used at the end of the iteration
     TC cv[PY], cp[PY];
@@ -275,7 +230,7 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
     for (int j = 0; j < PY; ++j) {
       const int o = valid[j] ? roff[j] + nplane * z : -1;
       cv[j] = bload<TC>(rv, boff<TC>(o, 0));
-      cp[j] = has_prev ? TC(bload<TO>(rp, boff<TO>(o, 0))) : TC(0);
+      cp[j] = TC(bload<TO>(rp, boff<TO>(o, 0)));
     }
     // advance the queue; fetch plane z+R+1
 #pragma unroll
@@ -301,6 +256,18 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
       const int po = zl + 1 < nzl ? plane_offset(z + 1, nplane, nz, a.per_z) : -1;
 #pragma unroll
       for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], po));
+    }
+    TC* nla = s_nl + ((zl & 1) ? plane_pts : 0);
+    if (NL) {  // projector term of plane zl into its (zeroed) accumulator, one writer per point
+      const int nrec = s_rp[zl + 1] - s_rp[zl];
+#pragma unroll
+      for (int r = 0; r < PY; ++r) {
+        if (tid + r * nthr < nrec) {
+          const unsigned c01 = (unsigned)hc[r][1], c23 = (unsigned)hc[r][2];
+          nla[hc[r][0]] = vc[r][0] * l_alpha[c01 & 0xffffu] + vc[r][1] * l_alpha[c01 >> 16] +
+                          vc[r][2] * l_alpha[c23 & 0xffffu] + vc[r][3] * l_alpha[c23 >> 16];
+        }
+      }
     }
     __syncthreads();
 
@@ -347,7 +314,6 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
         }
         acc[j] += t;
       }
-      TC* nla = s_nl + ((zl & 1) ? plane_pts : 0);
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
         if (!valid[j]) continue;
@@ -358,16 +324,29 @@ __global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
           hy += nla[li];
           nla[li] = TC(0);
         }
-        TC r = a.sa * (hy - a.sc * v);
-        if (has_prev) r += a.sb * cp[j];
-        ov[roff[j] + nplane * z] = TO(r);
+        ov[roff[j] + nplane * z] = TO(a.sa * (hy - a.sc * v) + a.sb * cp[j]);
       }
     }
     if (NL) {
-      finish_plane(zl + 1);
-      rc = rn;
+#pragma unroll
+      for (int r = 0; r < PY; ++r) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) hc[r][k] = hn[r][k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) vc[r][k] = vn[r][k];
+      }
     }
   }
+}
+
+size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes) {
+  size_t lds = 2 * (size_t)(p.ty + 2 * radius) * nx * elem_bytes;
+  if (np_tot >= 0) {
+    lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
+    lds += (size_t)((np_tot + 1) & ~1) * acc_bytes;
+    lds += 2 * (size_t)p.ty * nx * acc_bytes;
+  }
+  return lds;
 }
 
 HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override) {
@@ -386,12 +365,15 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
       const int threads = nx * nyg;
       const int waves = (threads + 63) / 64;
       if (2 * radius * nx > kHxMaxHalo * waves * 64) continue;  // halo values per thread bound
-      const size_t lds = 2 * (size_t)(ty + 2 * radius) * nx * elem_bytes + 2 * (size_t)ty * nx * 8;
+      const size_t lds = 2 * (size_t)(ty + 2 * radius) * nx * elem_bytes;
       if (lds > 48 * 1024) continue;
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
       const double halo = (double)(ty + 2 * radius) / ty;
       double cost = 1.0 / (lane_eff * row_eff) * (1.0 + 0.35 * (halo - 1.0));
+      // two rows per thread double the register queue and cost a wave of occupancy per
+      // SIMD (measured on 72^3 and 120^3: PY 1 wins unless its tiles get very thin)
+      if (py >= 2) cost *= 1.3;
       if (threads < 128) cost *= 1.15;
       if (ty > ny + 2 * radius) cost *= 2.0;
       if (cost < best_cost - 1e-12) {
@@ -426,21 +408,10 @@ static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, in
   a.nzc = p.nzc;
   a.nblocks = (int64_t)p.nty * p.nzc * ns;
   a.per_xcd = (int)((a.nblocks + 7) / 8);
-  size_t lds = 2 * (size_t)(p.ty + 2 * R) * a.nx * sizeof(TI);
-  a.alpha_lds = 0;
-  if (NL) {
-    lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
-    lds += 2 * (size_t)p.ty * a.nx * sizeof(TC);
-    const size_t al = (size_t)((a.np_tot + 1) & ~1) * sizeof(TC);
-    a.alpha_lds = (lds + al <= kHxMaxLds) ? 1 : 0;
-    if (a.alpha_lds) lds += al;
-  }
+  const size_t lds = hx_lds_bytes(p, a.nx, R, (int)sizeof(TI), NL ? a.np_tot : -1, (int)sizeof(TC));
   if (lds > kHxMaxLds) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(a.per_xcd * 8));
-  if (NL && a.alpha_lds)
-    hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL, true>), grid, dim3(p.threads), lds, s, a);
-  else
-    hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL, false>), grid, dim3(p.threads), lds, s, a);
+  hipLaunchKernelGGL((hx_apply_kernel<TI, TC, TO, R, PY, KH, NL>), grid, dim3(p.threads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -448,10 +419,8 @@ template <typename TI, typename TC, typename TO, int R, int PY>
 static hipError_t launch_rp(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int ns, hipStream_t s) {
   const bool nl = a.rec_ptr != nullptr;
   if (p.kh <= 2)
-    return nl ? launch_final<TI, TC, TO, R, PY, 2, true>(a, p, ns, s)
-              : launch_final<TI, TC, TO, R, PY, 2, false>(a, p, ns, s);
-  return nl ? launch_final<TI, TC, TO, R, PY, 4, true>(a, p, ns, s)
-            : launch_final<TI, TC, TO, R, PY, 4, false>(a, p, ns, s);
+    return nl ? launch_final<TI, TC, TO, R, PY, 2, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 2, false>(a, p, ns, s);
+  return nl ? launch_final<TI, TC, TO, R, PY, 4, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 4, false>(a, p, ns, s);
 }
 
 template <typename TI, typename TC, typename TO, int R>

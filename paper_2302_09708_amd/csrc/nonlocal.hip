@@ -5,8 +5,13 @@
 // The paper does this as one dense product per atom (chi_J^T X[S_J]).  Here a wave64
 // owns one atom and kV orbitals: it streams the atom's support indices and chi values
 // once, gathers the kV orbitals at those points (kV independent loads in flight per
-// step), and reduces across lanes in a fixed order (deterministic, no atomics).  The
-// scatter half, y[S_J] += chi_J alpha_J, is fused into hx_apply.
+// step), and reduces across lanes in a fixed order (deterministic, no atomics).
+//
+// nl_scatter: the other half, out[S_J] += sa * chi_J alpha_J, after hx_apply has written
+// the stencil, Veff and Chebyshev terms.  It runs per support point rather than per
+// atom: one thread owns a point and kS orbitals, sums the point's entries (every atom
+// whose support holds the point, in a fixed order) and updates each orbital once, so
+// no two threads touch one output and no atomics are needed.
 #include "common.h"
 
 namespace chefsi {
@@ -83,6 +88,46 @@ hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s) {
   hipLaunchKernelGGL((nl_project_kernel<TI, TC>), grid, dim3(64 * kNlWaves), 0, s, a);
   return hipGetLastError();
 }
+
+constexpr int kS = 8;  // orbitals per scatter thread
+
+template <typename TC, typename TO>
+__global__ __launch_bounds__(256) void nl_scatter_kernel(NsArgs<TC, TO> a) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.n_pts) return;
+  const int64_t v0 = (int64_t)blockIdx.y * kS;
+  const int4 r = a.rec[p];
+  const int pt = r.x, e0 = r.y, n = r.z;
+  const int nv = (int)min<int64_t>(kS, a.ns - v0);
+  const TC* al = a.alpha + v0 * a.np_tot;
+  TC sum[kS];
+#pragma unroll
+  for (int u = 0; u < kS; ++u) sum[u] = TC(0);
+  for (int e = e0; e < e0 + n; ++e) {
+    const int c = a.col[e];
+    const TC w = a.val[e];
+#pragma unroll
+    for (int u = 0; u < kS; ++u)
+      if (u < nv) sum[u] += w * al[(int64_t)u * a.np_tot + c];
+  }
+#pragma unroll
+  for (int u = 0; u < kS; ++u) {
+    if (u >= nv) break;
+    TO* o = a.out + (v0 + u) * a.nd + pt;
+    *o = TO(TC(*o) + a.sa * sum[u]);
+  }
+}
+
+template <typename TC, typename TO>
+hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
+  if (a.n_pts <= 0 || a.ns <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n_pts + 255) / 256), (unsigned)((a.ns + kS - 1) / kS));
+  hipLaunchKernelGGL((nl_scatter_kernel<TC, TO>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_nl_scatter<double, double>(const NsArgs<double, double>&, hipStream_t);
+template hipError_t launch_nl_scatter<float, float>(const NsArgs<float, float>&, hipStream_t);
 
 template hipError_t launch_nl_project<double, double>(const NlArgs<double, double>&, hipStream_t);
 template hipError_t launch_nl_project<float, float>(const NlArgs<float, float>&, hipStream_t);
