@@ -10,7 +10,9 @@
 namespace chefsi {
 
 constexpr int kMaxRadius = 6;  // finite-difference order up to 12
-constexpr int kHxMaxThreads = 512;  // stencil threads per block (keeps 256 VGPRs per lane)
+constexpr int kHxMaxThreads = 512;  // widest supported x row (one thread per x point)
+// stencil threads per block for PY rows per thread (1024 keeps 128 VGPRs per lane, 512 keeps 256)
+constexpr int hx_max_threads(int py) { return py == 1 ? 1024 : 512; }
 constexpr int kHxMaxHalo = 4;            // halo values each stencil thread stages per plane
 constexpr size_t kHxMaxLds = 96 * 1024;  // dynamic LDS of one stencil block (gfx950: 160 KB per CU)
 

@@ -105,8 +105,10 @@ __device__ __forceinline__ void load_rec(__amdgpu_buffer_rsrc_t r, unsigned off,
   }
 }
 
+// one row per thread fits 128 VGPRs, so its blocks may hold 1024 threads (taller tiles,
+// fewer halo rows per output row); two or more rows per thread keep 256 VGPRs and 512
 template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
-__global__ __launch_bounds__(512) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
+__global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   constexpr int Q = 2 * R + 1;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -350,15 +352,23 @@ size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_
 }
 
 HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override) {
+  // Cost of a tiling, fitted to measured launches on 72^3 and 120^3 grids (FP64 and FP32):
+  // idle lanes and rows beyond ny waste work, halo rows cost reads, blocks above 512
+  // threads and two rows per thread cost occupancy (more so in FP32 for the former and in
+  // FP64 for the latter).  Tiles of at least r+1 rows are required when any fit (thinner
+  // ones read the halo more than twice per output row and measured far slower).
   HxPlan best;
   double best_cost = 1e300;
+  bool best_tall = false;
   int nyg_override = 0;
   if (const char* e = std::getenv("CHEFSI_HX_NYG")) nyg_override = std::atoi(e);  // tiling experiments only
+  const double big_block = elem_bytes == 8 ? 1.2 : 1.35;
+  const double two_rows = elem_bytes == 8 ? 1.3 : 1.2;
   const int pys[] = {1, 2, 3, 4};
   for (int py : pys) {
     if (py_override > 0 && py != py_override) continue;
     if (py_override <= 0 && py > 2) continue;  // register queue budget (measured: PY 3-4 lose occupancy)
-    for (int nyg = 1; nx * nyg <= kHxMaxThreads; ++nyg) {
+    for (int nyg = 1; nx * nyg <= hx_max_threads(py); ++nyg) {
       if (nyg_override > 0 && nyg != nyg_override) continue;
       const int ty = nyg * py;
       const int nty = (ny + ty - 1) / ty;
@@ -370,13 +380,14 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
       const double halo = (double)(ty + 2 * radius) / ty;
-      double cost = 1.0 / (lane_eff * row_eff) * (1.0 + 0.35 * (halo - 1.0));
-      // two rows per thread double the register queue and cost a wave of occupancy per
-      // SIMD (measured on 72^3 and 120^3: PY 1 wins unless its tiles get very thin)
-      if (py >= 2) cost *= 1.3;
+      double cost = 1.0 / (lane_eff * row_eff) * (1.0 + 0.15 * (halo - 1.0));
+      if (threads > 512) cost *= big_block;
+      if (py >= 2) cost *= two_rows;
       if (threads < 128) cost *= 1.15;
       if (ty > ny + 2 * radius) cost *= 2.0;
-      if (cost < best_cost - 1e-12) {
+      const bool tall = ty >= std::min(radius + 1, ny);
+      if ((tall && !best_tall) || (tall == best_tall && cost < best_cost - 1e-12)) {
+        best_tall = tall;
         best_cost = cost;
         best.ok = true;
         best.py = py;
