@@ -189,6 +189,11 @@ size_t solver_workspace(chefsi_handle* h, int ns) {
     rocsolver_dsyevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr,
                      nullptr);
   });
+  if ((int64_t)h->nd * ns < ((int64_t)1 << 31))
+    query([&] {
+      rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)h->nd, ns, ns, &one,
+                    nullptr, (rocblas_int)h->nd, nullptr, ns, &one, nullptr, (rocblas_int)h->nd);
+    });
   h->solver_ws_cache[ns] = best;
   return best;
 }
@@ -571,6 +576,20 @@ void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hi
   if constexpr (std::is_same<T, float>::value) {
     if (g == Gemm::BF16X3) {
       HIP_TRY(launch_rotate_bf16x3(X, Z, at<void>(ws, L.zsplit), O, h->nd, ns, s));
+      ps.done();
+      return;
+    }
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    // FP64 X Z is a plain GEMM (nd x ns times ns x ns, no fusion): rocBLAS's MFMA kernel for
+    // it runs at a higher fraction of the FP64 peak than launch_rotate_f64.  Its 32-bit
+    // dimensions bound it to blocks of fewer than 2^31 elements.
+    if ((int64_t)h->nd * ns < ((int64_t)1 << 31)) {
+      const double one = 1.0, zero = 0.0;
+      BLAS_TRY(rocblas_set_stream(h->blas, s));
+      BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+      BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)h->nd, ns, ns,
+                             &one, X, (rocblas_int)h->nd, Z, ns, &zero, O, (rocblas_int)h->nd));
       ps.done();
       return;
     }
