@@ -108,14 +108,15 @@ def gemm_figures(nd: int, ns: int, prec: int, gram_ms: float, rot_ms: float, fp6
     """Algorithmic and executed MFMA flops of one step's projection (two Gram products) and rotation."""
     alg = 2.0 * nd * ns * (ns + 1) * 2 + 2.0 * nd * ns * ns
     nt = (ns + 127) // 128
-    gram_exec = 2 * (2.0 * nd * 128 * 128 * nt * (nt + 1) // 2)      # upper 128 x 128 tiles only
     if fp64:
+        gram_exec = 2 * (2.0 * nd * ns * ns)                          # rocBLAS dgemm: full Ns x Ns products
         rot_exec = 2.0 * nd * ns * ns
         mult, peak, unit_dtype = 1, FP64_MFMA_PEAK_TFS, "f64"
     else:
         ld = (ns + 31) // 32 * 32
         cols = (ns + 127) // 128 * 128
         rot_exec = 2.0 * ((nd + 255) // 256 * 256) * cols * ld
+        gram_exec = 2 * (2.0 * nd * 128 * 128 * nt * (nt + 1) // 2)  # upper 128 x 128 tiles only
         mult, peak, unit_dtype = 3, BF16_MFMA_PEAK_TFS, "bf16"   # three bf16 products per FP32 product
     t = (gram_ms + rot_ms) * 1e-3
     executed = mult * (gram_exec + rot_exec)

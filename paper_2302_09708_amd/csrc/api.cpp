@@ -145,11 +145,34 @@ struct chefsi_handle {
 
 namespace {
 
+// FP64 Gram products through rocBLAS as split-K: `splits` K chunks of kc rows as one
+// strided-batched dgemm, the tail rows (fewer than splits) as one more dgemm, and the
+// partial products summed in a fixed order.  Chunks are no shorter than 2048 rows and
+// about 4096 output tiles of 128 x 128 are in flight over all chunks.
+struct BlasGram {
+  int splits = 1;
+  int64_t kc = 0, tail = 0;
+  int nparts = 1;
+  size_t bytes = 0;
+};
+
+BlasGram plan_blas_gram(int64_t nd, int ns) {
+  BlasGram b;
+  const int64_t tiles = ((int64_t)(ns + 127) / 128) * ((ns + 127) / 128);
+  b.splits = (int)std::max<int64_t>(1, std::min<int64_t>({128, 4096 / tiles, nd / 2048}));
+  b.kc = nd / b.splits;
+  b.tail = nd - b.kc * b.splits;
+  b.nparts = b.splits + (b.tail > 0 ? 1 : 0);
+  b.bytes = (size_t)b.nparts * ns * ns * sizeof(double);
+  return b;
+}
+
 struct WsLayout {
   size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, sc = 0, info = 0, partial = 0, zsplit = 0, solver = 0,
          total = 0;
   size_t bufB_bytes = 0, solver_bytes = 0;
   GramPlan gram;
+  BlasGram bgram;  // FP64 handles: Gram products of FP64 blocks
 };
 
 // status words in the pinned staging buffer, after max_ns doubles
@@ -189,6 +212,14 @@ size_t solver_workspace(chefsi_handle* h, int ns) {
     rocsolver_dsyevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr,
                      nullptr);
   });
+  if (h->precision == CHEFSI_FP64) {
+    const BlasGram b = plan_blas_gram(h->nd, ns);
+    query([&] {
+      rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                                    (rocblas_int)b.kc, &one, nullptr, (rocblas_int)h->nd, b.kc, nullptr,
+                                    (rocblas_int)h->nd, b.kc, &one, nullptr, ns, (rocblas_stride)ns * ns, b.splits);
+    });
+  }
   if ((int64_t)h->nd * ns < ((int64_t)1 << 31))
     query([&] {
       rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)h->nd, ns, ns, &one,
@@ -220,8 +251,9 @@ WsLayout layout(chefsi_handle* h, int ns) {
   L.info = off;
   off += 256;
   L.gram = plan_gram(h->nd, ns);
+  L.bgram = plan_blas_gram(h->nd, ns);
   L.partial = off;
-  off += align256(L.gram.partial_bytes);
+  off += align256(std::max(L.gram.partial_bytes, h->precision == CHEFSI_FP64 ? L.bgram.bytes : (size_t)0));
   L.zsplit = off;
   if (h->precision == CHEFSI_MIXED) off += align256(zsplit_bytes(ns));
   L.solver = off;
@@ -453,10 +485,47 @@ hipError_t gram_launch(Gemm g, const TX* X, const TY* Y, int64_t nd, int ns, con
   return launch_gram_f64<TX, TY>(X, Y, nd, ns, p, part, s);
 }
 
+// C = X^T Y (upper triangle, mirrored) for FP64 blocks of an FP64 handle: rocBLAS's MFMA
+// dgemm over K chunks (a plain GEMM: no fusion to gain), partials summed in a fixed order.
+void blas_gram(chefsi_handle* h, const double* X, const double* Y, int ns, const WsLayout& L, void* ws, double* C,
+               hipStream_t s) {
+  double* part = at<double>(ws, L.partial);
+  const BlasGram& b = L.bgram;
+  const double one = 1.0, zero = 0.0;
+  const rocblas_int ld = (rocblas_int)h->nd;
+  {
+    ProfScope ps(h, P_GRAM, s);
+    BLAS_TRY(rocblas_set_stream(h->blas, s));
+    BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+    BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                                           (rocblas_int)b.kc, &one, X, ld, b.kc, Y, ld, b.kc, &zero, part, ns,
+                                           (rocblas_stride)ns * ns, b.splits));
+    if (b.tail > 0) {
+      const int64_t k0 = b.kc * b.splits;
+      BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                             (rocblas_int)b.tail, &one, X + k0, ld, Y + k0, ld, &zero,
+                             part + (size_t)b.splits * ns * ns, ns));
+    }
+    ps.done();
+  }
+  {
+    ProfScope ps(h, P_REDUCE, s);
+    HIP_TRY(launch_sum_partials(part, b.nparts, ns, C, s));
+    ps.done();
+  }
+}
+
 // Hs = X^T Y, Ms = X^T X (full symmetric, FP64), via split-K partial tiles.
 template <typename TX, typename TY>
 void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayout& L, void* ws, double* Hs,
                double* Ms, hipStream_t s, Gemm g) {
+  if constexpr (std::is_same<TX, double>::value && std::is_same<TY, double>::value) {
+    if (h->precision == CHEFSI_FP64) {
+      blas_gram(h, X, Y, ns, L, ws, Hs, s);
+      blas_gram(h, X, X, ns, L, ws, Ms, s);
+      return;
+    }
+  }
   double* part = at<double>(ws, L.partial);
   {
     ProfScope ps(h, P_GRAM, s);

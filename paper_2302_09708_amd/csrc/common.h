@@ -150,6 +150,10 @@ hipError_t launch_gram_f64(const TA* A, const TB* B, int64_t nd, int ns, const G
 
 hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, double* C, hipStream_t s);
 
+// C(i, j) = C(j, i) = sum over the nparts column-major ns x ns partial products P (upper
+// triangle read, summed in a fixed order).
+hipError_t launch_sum_partials(const double* P, int nparts, int ns, double* C, hipStream_t s);
+
 // Diagonal scaling of the pencil (Hs, Ms) by sc_i = Ms_ii^-1/2 (sc: ns doubles, written),
 // and the matching back-transformation Z(i, j) <- sc_i Z(i, j).
 hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipStream_t s);

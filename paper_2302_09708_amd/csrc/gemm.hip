@@ -158,6 +158,26 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   C[(int64_t)j + (int64_t)i * ns] = sum;
 }
 
+// C(i, j) = C(j, i) = sum_p P_p(i, j) for i <= j, P_p column-major ns x ns, summed in p order.
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ P, int nparts, int ns,
+                                                           double* __restrict__ C) {
+  const int64_t n2 = (int64_t)ns * ns;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n2) return;
+  const int j = (int)(e / ns), i = (int)(e % ns);
+  if (i > j) return;
+  double sum = 0.0;
+  for (int q = 0; q < nparts; ++q) sum += P[q * n2 + e];
+  C[e] = sum;
+  C[(int64_t)i * ns + j] = sum;
+}
+
+hipError_t launch_sum_partials(const double* P, int nparts, int ns, double* C, hipStream_t s) {
+  const int64_t n2 = (int64_t)ns * ns;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, P, nparts, ns, C);
+  return hipGetLastError();
+}
+
 GramPlan plan_gram(int64_t nd, int ns) {
   GramPlan p;
   p.tile = kTile;
