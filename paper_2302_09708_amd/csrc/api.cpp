@@ -846,6 +846,9 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       nd *= grid->n[d];
     }
     check(nd < (int64_t)1 << 31, "Nd must be below 2^31");
+    // the stencil pass addresses one orbital, Veff and the projector records (48 bytes per
+    // point at most) through buffer resources of fewer than 2^31 bytes
+    check(nd * 48 < (int64_t)1 << 31, "grids above 44 million points are not supported by the stencil pass");
     check(grid->n[0] <= kHxMaxThreads, "nx above 512 is not supported by the stencil tiling");
     check(max_ns >= 1 && (int64_t)max_ns <= nd, "max_ns must satisfy 1 <= max_ns <= Nd");
     for (int eb : {4, 8})

@@ -51,6 +51,12 @@ __device__ __forceinline__ int row_offset(int x, int gy, int nx, int ny, int per
   return (gy < 0 || gy >= ny) ? -1 : x + nx * gy;
 }
 
+// Periodic halo copies of element x in a tile row (pitch nx + 2r, element x at column
+// r + x; nx >= r): the right halo holds x < r at column r + nx + x, the left halo holds
+// x >= nx - r at column x - nx + r (with nx < 2r a point has both copies); -1 = none.
+__device__ __forceinline__ int xcopy_right(int x, int nx, int r) { return x < r ? r + nx + x : -1; }
+__device__ __forceinline__ int xcopy_left(int x, int nx, int r) { return x >= nx - r ? x - nx + r : -1; }
+
 // Offset of plane pz, or -1 for a Dirichlet zero plane.
 __device__ __forceinline__ int plane_offset(int pz, int nplane, int nz, int per_z) {
   if (per_z) return nplane * wrap_index(pz, nz);
@@ -61,43 +67,68 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-// element offsets -> byte offset, or out of range when either part is invalid (< 0)
+// Buffer loads take a per-lane byte offset (voff) and a wave-uniform one (soff, a scalar
+// register): the per-thread part of an address is computed once, the per-plane part on
+// the scalar unit, so a load costs no vector instructions.  A lane whose voff is kOOB
+// reads zero (kOOB + soff stays at or past the end because every buffer is below 2^31
+// bytes and so is soff).
 template <typename T>
-__device__ __forceinline__ unsigned boff(int a, int b) {
-  return (a < 0 || b < 0) ? kOOB : (unsigned)(a + b) * (unsigned)sizeof(T);
+__device__ __forceinline__ unsigned lane_off(int a) {
+  return a < 0 ? kOOB : (unsigned)a * (unsigned)sizeof(T);
 }
 
 template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off);
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
 template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
-// one projector record (zeros at kOOB): 32 bytes for FP32 values, 48 for FP64
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, T v, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, double v, unsigned voff, unsigned soff) {
+  typedef unsigned u32x2 __attribute__((__vector_size__(8)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// element at lane offset voff of plane po (element offset, uniform) of the nbytes-long
+// array at p; po = -1 (a zero plane) selects a resource with no records: reads give zero
+template <typename T>
+__device__ __forceinline__ T pload(const T* p, int nbytes, unsigned voff, int po) {
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(p, po < 0 ? 0 : nbytes);
+  return bload<T>(r, voff, po < 0 ? 0u : (unsigned)po * (unsigned)sizeof(T));
+}
+
+// one projector record (zeros when voff is kOOB): 32 bytes for FP32 values, 48 for FP64
 template <typename TC>
-__device__ __forceinline__ void load_rec(__amdgpu_buffer_rsrc_t r, unsigned off, int (&hdr)[3], TC (&v)[4]) {
-  const auto h = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+__device__ __forceinline__ void load_rec(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, int (&hdr)[3],
+                                         TC (&v)[4]) {
+  const auto h = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
   const unsigned h0 = h[0], h1 = h[1], h2 = h[2];
   hdr[0] = (int)h0;
   hdr[1] = (int)h1;
   hdr[2] = (int)h2;
-  const unsigned o1 = off == kOOB ? kOOB : off + 16u;
+  const unsigned o1 = voff + 16u;
   if constexpr (sizeof(TC) == 4) {
-    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, 0, 0);
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, soff, 0);
     const unsigned w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
     v[0] = __builtin_bit_cast(float, w0);
     v[1] = __builtin_bit_cast(float, w1);
     v[2] = __builtin_bit_cast(float, w2);
     v[3] = __builtin_bit_cast(float, w3);
   } else {
-    const unsigned o2 = off == kOOB ? kOOB : off + 32u;
-    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, 0, 0);
-    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, o2, 0, 0);
+    const unsigned o2 = voff + 32u;
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, o1, soff, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, o2, soff, 0);
     v[0] = __builtin_bit_cast(double, (unsigned long long)w[0] | ((unsigned long long)w[1] << 32));
     v[1] = __builtin_bit_cast(double, (unsigned long long)w[2] | ((unsigned long long)w[3] << 32));
     v[2] = __builtin_bit_cast(double, (unsigned long long)u[0] | ((unsigned long long)u[1] << 32));
@@ -130,7 +161,10 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
   const int nzl = z1 - z0;
 
   const int plane_pts = a.ty * nx;
-  const int tile_elems = (a.ty + 2 * R) * nx;
+  // LDS tile rows carry r halo columns on each side (periodic copies, or zeros for a
+  // Dirichlet x), so every x neighbour is a fixed offset from the thread's own element
+  const int pitch = nx + 2 * R;
+  const int tile_elems = (a.ty + 2 * R) * pitch;
   // LDS: [record offsets of this chunk][alpha row][projector term x2] (NL only) [tile plane x2]
   int* s_rp = reinterpret_cast<int*>(lds_raw);
   const int rp_slots = NL ? ((nzl + 1 + 3) & ~3) : 0;
@@ -144,14 +178,17 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
   const bool active = tid < nx * a.nyg;
   const int x = active ? tid % nx : 0;
   const int ly0 = active ? (tid / nx) * PY : 0;
+  const int xcr = active && a.per_x ? xcopy_right(x, nx, R) : -1;  // the thread's periodic x copies
+  const int xcl = active && a.per_x ? xcopy_left(x, nx, R) : -1;
   const int nplane = nx * ny;
-  const __amdgpu_buffer_rsrc_t rx = make_rsrc(a.x + vec * a.nd, a.nd * (int64_t)sizeof(TI));
+  const TI* xv = a.x + vec * a.nd;
+  const int xbytes = (int)(a.nd * (int64_t)sizeof(TI));
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.veff, a.nd * (int64_t)sizeof(TC));
   // with no previous iterate the resource has no records: its loads read zero
   const bool has_prev = a.prev != nullptr;
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(has_prev ? (const void*)(a.prev + vec * a.nd) : (const void*)a.out,
                                               has_prev ? a.nd * (int64_t)sizeof(TO) : 0);
-  TO* ov = a.out + vec * a.nd;
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + vec * a.nd, a.nd * (int64_t)sizeof(TO));
   const __amdgpu_buffer_rsrc_t rrec =
       make_rsrc(NL ? (const void*)a.rec : (const void*)a.out,
                 NL ? (int64_t)a.rec_ptr[a.nty * nz] * (int64_t)sizeof(HxRec<TC>) : 0);
@@ -164,10 +201,12 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
     for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
     __syncthreads();
+    const int rb = __builtin_amdgcn_readfirstlane(s_rp[0]), re = __builtin_amdgcn_readfirstlane(s_rp[1]);
 #pragma unroll
     for (int r = 0; r < PY; ++r) {
-      const int ri = s_rp[0] + tid + r * nthr;
-      load_rec<TC>(rrec, ri < s_rp[1] ? (unsigned)ri * (unsigned)sizeof(HxRec<TC>) : kOOB, hc[r], vc[r]);
+      const int i = tid + r * nthr;
+      load_rec<TC>(rrec, rb + i < re ? (unsigned)i * (unsigned)sizeof(HxRec<TC>) : kOOB,
+                   (unsigned)rb * (unsigned)sizeof(HxRec<TC>), hc[r], vc[r]);
     }
   }
 
@@ -179,7 +218,9 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     roff[j] = active ? row_offset(x, gy, nx, ny, a.per_y) : -1;
     valid[j] = active && gy < ny;
   }
-  int hoff[KH], hdst[KH];  // halo rows: local rows [0, R) and [R + ty, ty + 2R)
+  // halo rows (local rows [0, R) and [R + ty, ty + 2R)): source offset, LDS slot and the
+  // slots of its periodic x copies
+  int hoff[KH], hdst[KH], hdr[KH], hdl[KH];
   {
     const int nhalo = 2 * R * nx;
 #pragma unroll
@@ -187,14 +228,33 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
       const int e = tid + k * nthr;
       hoff[k] = -1;
       hdst[k] = -1;
+      hdr[k] = -1;
+      hdl[k] = -1;
       if (e < nhalo) {
         const int hr = e / nx, hxx = e % nx;
         const int yy = hr < R ? hr : hr + a.ty;
         hoff[k] = row_offset(hxx, y0 - R + yy, nx, ny, a.per_y);
-        hdst[k] = yy * nx + hxx;
+        hdst[k] = yy * pitch + R + hxx;
+        if (a.per_x) {
+          const int cr = xcopy_right(hxx, nx, R), cl = xcopy_left(hxx, nx, R);
+          hdr[k] = cr >= 0 ? yy * pitch + cr : -1;
+          hdl[k] = cl >= 0 ? yy * pitch + cl : -1;
+        }
       }
     }
   }
+
+  // lane byte offsets inside a plane: the thread's rows of x (vq), Veff (vv) and prev (vp)
+  // (kOOB for zero rows and rows past ny), and its halo values (vh)
+  unsigned vq[PY], vv[PY], vp[PY], vh[KH];
+#pragma unroll
+  for (int j = 0; j < PY; ++j) {
+    vq[j] = lane_off<TI>(roff[j]);
+    vv[j] = lane_off<TC>(valid[j] ? roff[j] : -1);
+    vp[j] = lane_off<TO>(valid[j] ? roff[j] : -1);
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k) vh[k] = lane_off<TI>(hoff[k]);
 
   // q[s][j] = plane (z - R + s); pf = plane z + R (fetched one plane ahead); hp = halo of plane z
   TI q[Q][PY], pf[PY], hp[KH];
@@ -204,35 +264,45 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
   for (int s = 1; s < Q; ++s) {
     const int po = plane_offset(z0 - R - 1 + s, nplane, nz, a.per_z);
 #pragma unroll
-    for (int j = 0; j < PY; ++j) q[s][j] = bload<TI>(rx, boff<TI>(roff[j], po));
+    for (int j = 0; j < PY; ++j) q[s][j] = pload<TI>(xv, xbytes, vq[j], po);
   }
   {
     const int po = plane_offset(z0 + R, nplane, nz, a.per_z);
 #pragma unroll
-    for (int j = 0; j < PY; ++j) pf[j] = bload<TI>(rx, boff<TI>(roff[j], po));
+    for (int j = 0; j < PY; ++j) pf[j] = pload<TI>(xv, xbytes, vq[j], po);
     const int ph = plane_offset(z0, nplane, nz, a.per_z);
 #pragma unroll
-    for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], ph));
+    for (int k = 0; k < KH; ++k) hp[k] = pload<TI>(xv, xbytes, vh[k], ph);
+  }
+
+  if (!a.per_x) {  // Dirichlet x: the halo columns of both tile buffers (never staged) hold zeros
+    const int nrows = 2 * (a.ty + 2 * R);
+    for (int i = tid; i < nrows * 2 * R; i += nthr) {
+      const int row = i / (2 * R), c = i % (2 * R);
+      s_tile[row * pitch + (c < R ? c : nx + c)] = TI(0);
+    }
   }
 
   for (int zl = 0; zl < nzl; ++zl) {
     const int z = z0 + zl;
     TI* tl = s_tile + (zl & 1) * tile_elems;
     if (NL) {  // records of plane zl + 1
+      const bool more = zl + 1 < nzl;
+      const int rb = more ? __builtin_amdgcn_readfirstlane(s_rp[zl + 1]) : 0;
+      const int re = more ? __builtin_amdgcn_readfirstlane(s_rp[zl + 2]) : 0;
 #pragma unroll
       for (int r = 0; r < PY; ++r) {
-        const int ri = zl + 1 < nzl ? s_rp[zl + 1] + tid + r * nthr : 0;
-        const bool ok = zl + 1 < nzl && ri < s_rp[zl + 2];
-        load_rec<TC>(rrec, ok ? (unsigned)ri * (unsigned)sizeof(HxRec<TC>) : kOOB, hn[r], vn[r]);
+        const int i = tid + r * nthr;
+        load_rec<TC>(rrec, rb + i < re ? (unsigned)i * (unsigned)sizeof(HxRec<TC>) : kOOB,
+                     (unsigned)rb * (unsigned)sizeof(HxRec<TC>), hn[r], vn[r]);
       }
     }
     // Veff and previous iterate of this plane, used at the end of the iteration
     TC cv[PY], cp[PY];
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
-      const int o = valid[j] ? roff[j] + nplane * z : -1;
-      cv[j] = bload<TC>(rv, boff<TC>(o, 0));
-      cp[j] = TC(bload<TO>(rp, boff<TO>(o, 0)));
+      cv[j] = bload<TC>(rv, vv[j], (unsigned)(nplane * z) * (unsigned)sizeof(TC));
+      cp[j] = TC(bload<TO>(rp, vp[j], (unsigned)(nplane * z) * (unsigned)sizeof(TO)));
     }
     // advance the queue; fetch plane z+R+1
 #pragma unroll
@@ -244,20 +314,27 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     {
       const int po = zl + 1 < nzl ? plane_offset(z + R + 1, nplane, nz, a.per_z) : -1;
 #pragma unroll
-      for (int j = 0; j < PY; ++j) pf[j] = bload<TI>(rx, boff<TI>(roff[j], po));
+      for (int j = 0; j < PY; ++j) pf[j] = pload<TI>(xv, xbytes, vq[j], po);
     }
-    // stage plane z in LDS; fetch the halo of plane z+1
+    // stage plane z in LDS (and the periodic x copies); fetch the halo of plane z+1
     if (active) {
 #pragma unroll
-      for (int j = 0; j < PY; ++j) tl[(R + ly0 + j) * nx + x] = q[R][j];
+      for (int j = 0; j < PY; ++j) {
+        tl[(R + ly0 + j) * pitch + R + x] = q[R][j];
+        if (xcr >= 0) tl[(R + ly0 + j) * pitch + xcr] = q[R][j];
+        if (xcl >= 0) tl[(R + ly0 + j) * pitch + xcl] = q[R][j];
+      }
     }
 #pragma unroll
-    for (int k = 0; k < KH; ++k)
+    for (int k = 0; k < KH; ++k) {
       if (hdst[k] >= 0) tl[hdst[k]] = hp[k];
+      if (hdr[k] >= 0) tl[hdr[k]] = hp[k];
+      if (hdl[k] >= 0) tl[hdl[k]] = hp[k];
+    }
     {
       const int po = zl + 1 < nzl ? plane_offset(z + 1, nplane, nz, a.per_z) : -1;
 #pragma unroll
-      for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(rx, boff<TI>(hoff[k], po));
+      for (int k = 0; k < KH; ++k) hp[k] = pload<TI>(xv, xbytes, vh[k], po);
     }
     TC* nla = s_nl + ((zl & 1) ? plane_pts : 0);
     if (NL) {  // projector term of plane zl into its (zeroed) accumulator, one writer per point
@@ -285,7 +362,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
       // y part: each LDS row of the column is read once and feeds every row it neighbours
 #pragma unroll
       for (int t = 0; t < PY + 2 * R; ++t) {
-        const TC v = TC(tl[(ly0 + t) * nx + x]);
+        const TC v = TC(tl[(ly0 + t) * pitch + R + x]);
 #pragma unroll
         for (int j = 0; j < PY; ++j) {
           const int p = t - R - j;
@@ -295,25 +372,10 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
       // x part: neighbours inside the row
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
-        const TI* row = tl + (R + ly0 + j) * nx;
+        const TI* row = tl + (R + ly0 + j) * pitch + R + x;
         TC t = TC(0);
-        if (a.per_x) {
 #pragma unroll
-          for (int p = 1; p <= R; ++p) {
-            int xp = x + p;
-            xp = xp >= nx ? xp - nx : xp;
-            int xm = x - p;
-            xm = xm < 0 ? xm + nx : xm;
-            t += a.cx[p] * (TC(row[xp]) + TC(row[xm]));
-          }
-        } else {
-#pragma unroll
-          for (int p = 1; p <= R; ++p) {
-            const TC vp = (x + p < nx) ? TC(row[x + p]) : TC(0);
-            const TC vm = (x - p >= 0) ? TC(row[x - p]) : TC(0);
-            t += a.cx[p] * (vp + vm);
-          }
-        }
+        for (int p = 1; p <= R; ++p) t += a.cx[p] * (TC(row[p]) + TC(row[-p]));
         acc[j] += t;
       }
 #pragma unroll
@@ -326,7 +388,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
           hy += nla[li];
           nla[li] = TC(0);
         }
-        ov[roff[j] + nplane * z] = TO(a.sa * (hy - a.sc * v) + a.sb * cp[j]);
+        bstore<TO>(ro, TO(a.sa * (hy - a.sc * v) + a.sb * cp[j]), vp[j], (unsigned)(nplane * z) * (unsigned)sizeof(TO));
       }
     }
     if (NL) {
@@ -342,7 +404,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
 }
 
 size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes) {
-  size_t lds = 2 * (size_t)(p.ty + 2 * radius) * nx * elem_bytes;
+  size_t lds = 2 * (size_t)(p.ty + 2 * radius) * (nx + 2 * radius) * elem_bytes;
   if (np_tot >= 0) {
     lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
     lds += (size_t)((np_tot + 1) & ~1) * acc_bytes;
@@ -375,7 +437,7 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
       const int threads = nx * nyg;
       const int waves = (threads + 63) / 64;
       if (2 * radius * nx > kHxMaxHalo * waves * 64) continue;  // halo values per thread bound
-      const size_t lds = 2 * (size_t)(ty + 2 * radius) * nx * elem_bytes;
+      const size_t lds = 2 * (size_t)(ty + 2 * radius) * (nx + 2 * radius) * elem_bytes;
       if (lds > 48 * 1024) continue;
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
