@@ -100,6 +100,8 @@ struct NlArgs {
   const TC* gdv;           // gamma * dV per projector column
   TC* alpha;
   int np_tot;
+  int ngroups;  // orbital groups per atom (set by the launcher)
+  int per_xcd;  // blocks per XCD (set by the launcher)
 };
 
 template <typename TI, typename TC>

@@ -31,8 +31,13 @@ template <typename TI, typename TC>
 __global__ __launch_bounds__(256) void nl_project_kernel(NlArgs<TI, TC> a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int atom = blockIdx.x;
-  const int64_t v0 = ((int64_t)blockIdx.y * kNlWaves + wave) * kNlV;
+  // the hardware deals consecutive block ids to the 8 XCDs in turn; each XCD takes a
+  // contiguous run of logical ids, atom fastest, so atoms with overlapping supports (close
+  // in the atom order) read their shared points through one L2
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+  if (logical >= (int64_t)a.n_atoms * a.ngroups) return;
+  const int atom = (int)(logical % a.n_atoms);
+  const int64_t v0 = ((logical / a.n_atoms) * kNlWaves + wave) * kNlV;
   if (v0 >= a.ns) return;  // whole wave exits together; no block barrier below
   const int s0 = a.supp_off[atom];
   const int n = a.supp_off[atom + 1] - s0;
@@ -84,8 +89,11 @@ template <typename TI, typename TC>
 hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s) {
   if (a.n_atoms <= 0 || a.ns <= 0) return hipSuccess;
   const int per_block = kNlWaves * kNlV;
-  dim3 grid((unsigned)a.n_atoms, (unsigned)((a.ns + per_block - 1) / per_block));
-  hipLaunchKernelGGL((nl_project_kernel<TI, TC>), grid, dim3(64 * kNlWaves), 0, s, a);
+  NlArgs<TI, TC> b = a;
+  b.ngroups = (a.ns + per_block - 1) / per_block;
+  const int64_t nb = (int64_t)a.n_atoms * b.ngroups;
+  b.per_xcd = (int)((nb + 7) / 8);
+  hipLaunchKernelGGL((nl_project_kernel<TI, TC>), dim3((unsigned)(b.per_xcd * 8)), dim3(64 * kNlWaves), 0, s, b);
   return hipGetLastError();
 }
 
