@@ -99,11 +99,19 @@ hipError_t launch_nl_project(const NlArgs<TI, TC>& a, hipStream_t s) {
 
 constexpr int kS = 8;  // orbitals per scatter thread
 
+// Blocks are dealt to the 8 XCDs in turn; XCD k owns the k-th slab of npb8 point blocks
+// and runs it for every orbital group, so the slab's entries stay in that XCD's L2 while
+// the groups go by (dealt group by group, every XCD would cycle through all entries).
 template <typename TC, typename TO>
-__global__ __launch_bounds__(256) void nl_scatter_kernel(NsArgs<TC, TO> a) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void nl_scatter_kernel(NsArgs<TC, TO> a, int npb8, int ngroups) {
+  const int xcd = blockIdx.x % 8;
+  const int j = blockIdx.x / 8;
+  const int group = j / npb8;
+  const int pb = xcd * npb8 + j % npb8;
+  if (group >= ngroups) return;
+  const int p = pb * 256 + threadIdx.x;
   if (p >= a.n_pts) return;
-  const int64_t v0 = (int64_t)blockIdx.y * kS;
+  const int64_t v0 = (int64_t)group * kS;
   const int4 r = a.rec[p];
   const int pt = r.x, e0 = r.y, n = r.z;
   const int nv = (int)min<int64_t>(kS, a.ns - v0);
@@ -129,8 +137,11 @@ __global__ __launch_bounds__(256) void nl_scatter_kernel(NsArgs<TC, TO> a) {
 template <typename TC, typename TO>
 hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
   if (a.n_pts <= 0 || a.ns <= 0) return hipSuccess;
-  dim3 grid((unsigned)((a.n_pts + 255) / 256), (unsigned)((a.ns + kS - 1) / kS));
-  hipLaunchKernelGGL((nl_scatter_kernel<TC, TO>), grid, dim3(256), 0, s, a);
+  const int npb = (a.n_pts + 255) / 256;
+  const int npb8 = (npb + 7) / 8;
+  const int ngroups = (a.ns + kS - 1) / kS;
+  hipLaunchKernelGGL((nl_scatter_kernel<TC, TO>), dim3((unsigned)(8 * npb8 * ngroups)), dim3(256), 0, s, a, npb8,
+                     ngroups);
   return hipGetLastError();
 }
 
