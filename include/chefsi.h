@@ -137,6 +137,26 @@ int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
  * Host arithmetic only; any output pointer may be NULL. */
 int chefsi_spectral_bounds(const chefsi_handle_t* h, double* lam_lo, double* lam_cut, double* lam_hi);
 
+/* Estimate of lam_Nd, the largest eigenvalue of H (Alg. 1, the top of the filter
+ * interval), by `steps` Lanczos steps from the start vector v0 (library reading; the
+ * paper does not say how lam_Nd is found):
+ *   w = H v_j - beta_{j-1} v_{j-1},  alpha_j = v_j^T w,  w -= alpha_j v_j,
+ *   beta_j = ||w||,  v_{j+1} = w / beta_j   (v_1 = v0 / ||v0||, no reorthogonalisation).
+ * theta = largest eigenvalue of tridiag(beta, alpha, beta) (a Ritz value, never above
+ * lam_Nd); *lam_nd = theta + |beta_k s_k| with s the unit eigenvector of the
+ * tridiagonal matrix for theta, i.e. theta plus the Ritz pair's residual norm.
+ * v0: device vector of Nd elements in the handle's storage type (FP64 handle: double,
+ * mixed handle: float), not modified; products with H and all sums in FP64, orbital
+ * vectors stored in the storage type.  ws: caller-owned device memory of
+ * chefsi_lanczos_workspace_bytes() bytes.  Synchronises the stream (the coefficients
+ * steer the recurrence from the host).  alpha_host/beta_host (optional, `steps`
+ * doubles each) receive the coefficients, zeros past an early stop (beta = 0).
+ * Errors: ERR_INVALID_ARG (NULL pointers, steps outside 1..1000, zero or non-finite
+ * v0), ERR_WORKSPACE, ERR_NONFINITE, ERR_HIP. */
+int chefsi_lanczos_workspace_bytes(const chefsi_handle_t* h, size_t* bytes);
+int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void* ws, size_t ws_bytes,
+                         void* stream, double* lam_nd, double* theta, double* alpha_host, double* beta_host);
+
 /* Y = H X for an Nd x ns block (Sec. 2.1: stencil + Veff + nonlocal).  X and Y
  * are distinct device blocks of the handle's element type. */
 int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns,

@@ -39,7 +39,7 @@ EXPORTS = (
     "chefsi_apply_h", "chefsi_filter", "chefsi_project", "chefsi_eigh", "chefsi_rotate",
     "chefsi_step", "chefsi_solve", "chefsi_refine_fp64", "chefsi_profile_enable",
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
-    "chefsi_last_error", "chefsi_version",
+    "chefsi_last_error", "chefsi_version", "chefsi_lanczos_workspace_bytes", "chefsi_lanczos_bound",
 )
 
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.chefsi_handle_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_lanczos_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+    lib.chefsi_lanczos_bound.argtypes = [vp, vp, i32, vp, sz, vp, pd, pd, pd, pd]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
     lib.chefsi_project.argtypes = [vp, vp, i32, vp, vp, vp, sz, vp]
     lib.chefsi_eigh.argtypes = [vp, vp, vp, vp, i32, vp, sz, vp]
@@ -198,6 +200,21 @@ class Handle:
         lo, cut, hi = C.c_double(), C.c_double(), C.c_double()
         self._check(self._lib.chefsi_spectral_bounds(self.h, C.byref(lo), C.byref(cut), C.byref(hi)))
         return lo.value, cut.value, hi.value
+
+    def chefsi_lanczos_workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_lanczos_workspace_bytes(self.h, C.byref(b)))
+        return int(b.value)
+
+    def chefsi_lanczos_bound(self, v0, steps, ws, ws_bytes=None, stream=None):
+        """(lam_nd, theta, alphas, betas) of `steps` Lanczos steps from the device vector v0."""
+        lam, th = C.c_double(), C.c_double()
+        a = np.zeros(int(steps))
+        b = np.zeros(int(steps))
+        self._check(self._lib.chefsi_lanczos_bound(
+            self.h, _ptr(v0), int(steps), _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream), C.byref(lam),
+            C.byref(th), a.ctypes.data_as(C.POINTER(C.c_double)), b.ctypes.data_as(C.POINTER(C.c_double))))
+        return lam.value, th.value, a, b
 
     def chefsi_apply_h(self, X, Y, ns, ws, ws_bytes=None, stream=None):
         self._check(self._lib.chefsi_apply_h(self.h, _ptr(X), _ptr(Y), int(ns), _ptr(ws),

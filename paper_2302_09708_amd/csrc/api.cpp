@@ -1258,6 +1258,171 @@ int chefsi_refine_fp64(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree, 
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Lanczos estimate of lam_Nd (Alg. 1: the largest eigenvalue of H).
+// Workspace: v_{j-1}, v_j (storage type), w (FP64), the projector coefficients of one
+// vector (FP64), the block sums and two result words.
+// ---------------------------------------------------------------------------
+struct LzLayout {
+  size_t v0 = 0, v1 = 0, w = 0, alpha = 0, partial = 0, out = 0, total = 0;
+};
+
+LzLayout lanczos_layout(const chefsi_handle* h) {
+  LzLayout L;
+  const size_t vb = (size_t)h->nd * elem_bytes(h);
+  size_t off = 0;
+  L.v0 = off;
+  off += align256(vb);
+  L.v1 = off;
+  off += align256(vb);
+  L.w = off;
+  off += align256((size_t)h->nd * 8);
+  L.alpha = off;
+  off += align256((size_t)std::max(1, h->np_tot) * 8);
+  L.partial = off;
+  off += align256((size_t)kVecBlocks * 8);
+  L.out = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+// Largest eigenvalue theta of the symmetric tridiagonal T (diagonal a[0..k), off-diagonal
+// b[0..k-1)) by Sturm-count bisection to full precision, and the last component of its
+// unit eigenvector by two steps of inverse iteration (T - theta I with a tiny shift).
+void tridiagonal_top(const std::vector<double>& a, const std::vector<double>& b, double* theta, double* s_last) {
+  const int k = (int)a.size();
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_above = [&](double x) {  // eigenvalues > x (Sturm sequence of T - x I)
+    int neg = 0;
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      d = (a[i] - x) - (i > 0 ? bb / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++neg;
+    }
+    return k - neg;
+  };
+  for (int it = 0; it < 200 && hi - lo > 2e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_above(mid) >= 1) lo = mid; else hi = mid;
+  }
+  *theta = 0.5 * (lo + hi);
+  if (k == 1) {
+    *s_last = 1.0;
+    return;
+  }
+  const double shift = *theta + 1e-13 * std::max(1.0, std::fabs(*theta));
+  std::vector<double> x(k, 1.0), c(k), d(k), y(k);
+  for (int rep = 0; rep < 3; ++rep) {  // solve (T - shift I) y = x (tridiagonal LU, no pivoting)
+    for (int i = 0; i < k; ++i) {
+      d[i] = a[i] - shift;
+      y[i] = x[i];
+    }
+    for (int i = 1; i < k; ++i) {
+      const double m = b[i - 1] / d[i - 1];
+      d[i] -= m * b[i - 1];
+      y[i] -= m * y[i - 1];
+    }
+    x[k - 1] = y[k - 1] / d[k - 1];
+    for (int i = k - 2; i >= 0; --i) x[i] = (y[i] - b[i] * x[i + 1]) / d[i];
+    double nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (double& v : x) v /= nrm;
+  }
+  *s_last = x[k - 1];
+}
+
+template <typename TV>
+void lanczos_impl(chefsi_handle* h, const TV* v0, int steps, void* ws, const LzLayout& L, hipStream_t s,
+                  std::vector<double>& a, std::vector<double>& b) {
+  TV* vb[2] = {at<TV>(ws, L.v0), at<TV>(ws, L.v1)};
+  double* w = at<double>(ws, L.w);
+  double* part = at<double>(ws, L.partial);
+  double* out = at<double>(ws, L.out);
+  double* pin = h->pinned;
+  auto read_scalar = [&]() {
+    HIP_TRY(hipMemcpyAsync(pin, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return pin[0];
+  };
+  // v_1 = v0 / ||v0||
+  HIP_TRY(launch_widen<TV>(v0, h->nd, w, s));
+  HIP_TRY(launch_lanczos_norm<TV>(w, nullptr, 0.0, h->nd, part, out, s));
+  const double n0 = std::sqrt(read_scalar());
+  check(std::isfinite(n0) && n0 > 0.0, "the start vector must be finite and nonzero");
+  HIP_TRY(launch_lanczos_scale<TV>(w, 1.0 / n0, h->nd, vb[0], s));
+  int cur = 0;
+  double beta = 0.0;
+  for (int j = 0; j < steps; ++j) {
+    const TV* v = vb[cur];
+    TV* vprev = vb[cur ^ 1];
+    apply_fused<TV, double, double>(h, v, nullptr, w, 1, 1.0, 0.0, 0.0, at<double>(ws, L.alpha), s);
+    HIP_TRY(launch_lanczos_dot<TV>(w, v, j > 0 ? vprev : nullptr, beta, h->nd, part, out, s));
+    const double alpha = read_scalar();
+    HIP_TRY(launch_lanczos_norm<TV>(w, v, alpha, h->nd, part, out, s));
+    beta = std::sqrt(read_scalar());
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) throw Error{CHEFSI_ERR_NONFINITE, "non-finite Lanczos coefficient"};
+    a.push_back(alpha);
+    b.push_back(beta);
+    if (beta == 0.0) break;
+    HIP_TRY(launch_lanczos_scale<TV>(w, 1.0 / beta, h->nd, vprev, s));  // v_{j+1} over v_{j-1}
+    cur ^= 1;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int chefsi_lanczos_workspace_bytes(const chefsi_handle_t* hc, size_t* bytes) {
+  chefsi_handle* h = const_cast<chefsi_handle*>(hc);
+  return guarded(h, [&] {
+    check(bytes != nullptr, "bytes is NULL");
+    *bytes = lanczos_layout(h).total;
+  });
+}
+
+int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void* ws, size_t ws_bytes, void* stream,
+                         double* lam_nd, double* theta, double* alpha_host, double* beta_host) {
+  return guarded(h, [&] {
+    check(v0 != nullptr && ws != nullptr, "v0 and ws must be device buffers");
+    check(steps >= 1 && steps <= 1000, "steps must be in 1..1000");
+    check(lam_nd != nullptr, "lam_nd is NULL");
+    const LzLayout L = lanczos_layout(h);
+    if (ws_bytes < L.total) throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_lanczos_workspace_bytes"};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> a, b;
+    if (h->precision == CHEFSI_FP64)
+      lanczos_impl<double>(h, (const double*)v0, steps, ws, L, s, a, b);
+    else
+      lanczos_impl<float>(h, (const float*)v0, steps, ws, L, s, a, b);
+    double th = 0.0, sl = 0.0;
+    tridiagonal_top(a, b, &th, &sl);
+    *lam_nd = th + std::fabs(b.back() * sl);
+    if (theta) *theta = th;
+    for (size_t i = 0; i < a.size(); ++i) {
+      if (alpha_host) alpha_host[i] = a[i];
+      if (beta_host) beta_host[i] = b[i];
+    }
+    for (size_t i = a.size(); i < (size_t)steps; ++i) {  // stopped early (invariant subspace)
+      if (alpha_host) alpha_host[i] = 0.0;
+      if (beta_host) beta_host[i] = 0.0;
+    }
+  });
+}
+
 int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes) {
   if (h == nullptr || bytes == nullptr) return CHEFSI_ERR_INVALID_ARG;
   *bytes = h->device_bytes;

@@ -175,4 +175,25 @@ size_t zsplit_bytes(int ns);
 hipError_t launch_rotate_bf16x3(const float* X, const double* Z, void* zsplit, float* O, int64_t nd, int ns,
                                 hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Lanczos vector kernels (fixed grid of kVecBlocks x kVecThreads, fixed-order sums).
+// dot:   w -= beta vp (vp may be null); out[0] = v . w
+// norm:  w -= alpha v (v may be null);  out[0] = w . w
+// scale: out = TV(w * inv);  widen: w = double(x)
+// partial: kVecBlocks doubles of scratch.
+// ---------------------------------------------------------------------------
+constexpr int kVecThreads = 256;
+constexpr int kVecBlocks = 1024;
+
+template <typename TV>
+hipError_t launch_lanczos_dot(double* w, const TV* v, const TV* vp, double beta, int64_t n, double* partial,
+                              double* out, hipStream_t s);
+template <typename TV>
+hipError_t launch_lanczos_norm(double* w, const TV* v, double alpha, int64_t n, double* partial, double* out,
+                               hipStream_t s);
+template <typename TV>
+hipError_t launch_lanczos_scale(const double* w, double inv, int64_t n, TV* out, hipStream_t s);
+template <typename TV>
+hipError_t launch_widen(const TV* x, int64_t n, double* w, hipStream_t s);
+
 }  // namespace chefsi
