@@ -197,6 +197,48 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
     return out
 
 
+def lanczos_figures(cs, prob, cfg, precision: str, steps: int = 20):
+    """Device Lanczos estimate of lam_Nd on the workload (outside the timed steps): time of
+    `steps` steps, the estimate and the Gershgorin bound the timed steps start from."""
+    import torch
+    from paper_2302_09708_amd import inputs
+    prec = cs.FP64 if precision == "fp64" else cs.MIXED
+    h = cs.Handle(prob, precision=prec, max_ns=1)
+    ws = torch.empty(h.chefsi_lanczos_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    v = torch.from_numpy(inputs.initial_block(prob.nd, 1, cfg.x_seed + 1)[0]).to(
+        device="cuda", dtype=torch.float64 if prec == cs.FP64 else torch.float32)
+    h.chefsi_lanczos_bound(v, steps, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, theta, _, _ = h.chefsi_lanczos_bound(v, steps, ws)
+    ms = (time.perf_counter() - t0) * 1e3
+    gersh = h.chefsi_spectral_bounds()[2]
+    h.close()
+    del ws, v
+    torch.cuda.empty_cache()
+    return {"steps": steps, "ms": ms, "theta": theta, "lam_nd": lam, "gershgorin_lam_hi": gersh}
+
+
+def copy_gbs():
+    """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes / time), the
+    practical streaming ceiling the stencil's rate is also compared with."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / best / 1e9
+
+
 def serving_bench(args):
     """Serving stream: Poisson arrivals of CheFSI solve requests of mixed sizes, continuous
     admission by slot and HBM footprint; p50/p99 latency and solves/s."""
@@ -283,6 +325,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    lz = lanczos_figures(cs, prob, cfg, precision)
+    cgbs = copy_gbs()
     kern = main_run["kernels"]
     # the dominant kernel among those with a roofline (the FP64 dense stage and copies have none)
     dominant = max(("hx_apply", "gram", "rotate"), key=lambda k: kern[k]["ms_per_step"])
@@ -300,7 +344,8 @@ def main():
         roof = {"bound": "hbm", "kernel": "hx_apply", "achieved": main_run["hx_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": main_run["hx_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": main_run["hx_bytes_step"] / hx_launches,
-                "avg_launch_ms": kern["hx_apply"]["avg_launch_ms"]}
+                "avg_launch_ms": kern["hx_apply"]["avg_launch_ms"],
+                "copy_gbs": cgbs, "frac_of_copy": main_run["hx_gbs"] / cgbs}
 
     out = {
         "metric": "CheFSI iter/s",
@@ -325,6 +370,7 @@ def main():
         "gemm": g,
         "kernels": kern,
         "solve_ms": main_run["solve_ms"],
+        "lanczos_lam_nd": lz,
     }
     if other is not None:
         out["compare"] = {
