@@ -115,6 +115,15 @@ typedef struct {
 int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
                   int32_t precision, int32_t max_ns, chefsi_handle_t** out);
 
+/* Replace the handle's local potential (the SCF loop changes Veff between CheFSI calls
+ * while grid and projectors stay; Alg. 1 takes H for a given SCF iteration): veff_host
+ * holds Nd FP64 values in the grid order of chefsi_create, copied, so the caller may
+ * free it on return.  The copies are ordered on `stream`, which is synchronised; work of
+ * this handle on other streams must have completed.  chefsi_spectral_bounds and every
+ * later call use the new potential.  Errors: ERR_INVALID_ARG (NULL or non-finite
+ * values; the handle keeps its old Veff), ERR_HIP. */
+int chefsi_update_veff(chefsi_handle_t* h, const double* veff_host, void* stream);
+
 /* Release everything the handle owns.  NULL is ignored. */
 void chefsi_destroy(chefsi_handle_t* h);
 

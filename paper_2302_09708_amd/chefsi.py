@@ -40,6 +40,7 @@ EXPORTS = (
     "chefsi_step", "chefsi_solve", "chefsi_refine_fp64", "chefsi_profile_enable",
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
     "chefsi_last_error", "chefsi_version", "chefsi_lanczos_workspace_bytes", "chefsi_lanczos_bound",
+    "chefsi_update_veff",
 )
 
 
@@ -85,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.chefsi_handle_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_update_veff.argtypes = [vp, pd, vp]
     lib.chefsi_lanczos_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_lanczos_bound.argtypes = [vp, vp, i32, vp, sz, vp, pd, pd, pd, pd]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
@@ -200,6 +202,12 @@ class Handle:
         lo, cut, hi = C.c_double(), C.c_double(), C.c_double()
         self._check(self._lib.chefsi_spectral_bounds(self.h, C.byref(lo), C.byref(cut), C.byref(hi)))
         return lo.value, cut.value, hi.value
+
+    def chefsi_update_veff(self, veff, stream=None):
+        v = np.ascontiguousarray(veff, dtype=np.float64).reshape(-1)
+        if v.size != self.nd:
+            raise ValueError(f"Veff has {v.size} values, the grid {self.nd}")
+        self._check(self._lib.chefsi_update_veff(self.h, v.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
 
     def chefsi_lanczos_workspace_bytes(self) -> int:
         b = C.c_size_t()

@@ -817,6 +817,19 @@ const char* chefsi_last_error(const chefsi_handle_t* h) { return h ? h->last_err
 
 int chefsi_last_info(const chefsi_handle_t* h) { return h ? h->last_info : 0; }
 
+int chefsi_update_veff(chefsi_handle_t* h, const double* veff_host, void* stream) {
+  return guarded(h, [&] {
+    check(veff_host != nullptr, "veff_host is NULL");
+    for (int64_t i = 0; i < h->nd; ++i) check(std::isfinite(veff_host[i]), "Veff must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    h->veff_h.assign(veff_host, veff_host + h->nd);
+    const std::vector<float> v32(h->veff_h.begin(), h->veff_h.end());
+    HIP_TRY(hipMemcpyAsync(h->veff64, h->veff_h.data(), (size_t)h->nd * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->veff32, v32.data(), (size_t)h->nd * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // v32 and the caller's array may go away after return
+  });
+}
+
 int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
                   int32_t precision, int32_t max_ns, chefsi_handle_t** out) {
   if (out == nullptr) return CHEFSI_ERR_INVALID_ARG;
