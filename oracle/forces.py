@@ -1,0 +1,78 @@
+"""Nonlocal (Kleinman-Bylander) part of the Hellmann-Feynman atomic forces (oracle; test
+infrastructure only).
+
+Sec. 2 of the paper: the stencil and projector routines of the filter are reused for the
+nonlocal components of the forces and stresses, whose key kernels are the gradient
+operator applied to the Kohn-Sham orbitals followed by the nonlocal projectors applied to
+the result.  For real orbitals psi_n with occupations g_n the nonlocal energy is
+
+    E_nl = sum_n g_n sum_{J,a} gamma_Ja (dV chi_Ja^T psi_n)^2 .
+
+Moving atom J moves chi_Ja(r - R_J); integration by parts (periodic directions, or
+orbitals that vanish at a Dirichlet boundary) turns d(chi^T psi)/dR_J into chi^T grad psi:
+
+    F_J = -dE_nl/dR_J = -2 sum_n g_n sum_a gamma_Ja (dV chi_Ja^T psi_n) (dV chi_Ja^T grad psi_n).
+
+grad is the central finite-difference first derivative of the same order 2r as the
+Laplacian, with the closed-form weights (limit of Lagrange interpolation on 2r+1 nodes)
+
+    d psi / dx_d (i) ~ (1/h_d) sum_{p=1..r} c_p (psi[i + p e_d] - psi[i - p e_d]),
+    c_p = (-1)^(p+1) (r!)^2 / (p (r-p)! (r+p)!).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .hamiltonian import _shift, atom_blocks
+
+
+def first_derivative_weights(order: int) -> np.ndarray:
+    """c_1..c_r (index 0 unused, zero) of the central first-derivative stencil of even ``order``."""
+    if order < 2 or order % 2:
+        raise ValueError("finite-difference order must be even and >= 2")
+    r = order // 2
+    c = np.zeros(r + 1)
+    for p in range(1, r + 1):
+        c[p] = (-1.0) ** (p + 1) * math.factorial(r) ** 2 / (p * math.factorial(r - p) * math.factorial(r + p))
+    return c
+
+
+def gradient(prob, x: np.ndarray, direction: int) -> np.ndarray:
+    """d x / d x_direction for an (Nd, Ns) block (periodic wrap or zero ghosts)."""
+    nx, ny, nz = prob.n
+    c = first_derivative_weights(prob.fd_order)
+    ns = x.shape[1]
+    u = np.asarray(x, dtype=np.float64).reshape(nz, ny, nx, ns)
+    periodic = prob.bc[direction] == 0
+    g = np.zeros_like(u)
+    for p in range(1, len(c)):
+        g += c[p] * (_shift(u, p, direction, periodic) - _shift(u, -p, direction, periodic))
+    return (g / prob.h[direction]).reshape(-1, ns)
+
+
+def nonlocal_forces(prob, psi: np.ndarray, occ: np.ndarray) -> np.ndarray:
+    """(n_atoms, 3) nonlocal forces for orbitals psi (Nd x Ns) with occupations occ (Ns)."""
+    dv = prob.h[0] * prob.h[1] * prob.h[2]
+    psi = np.asarray(psi, dtype=np.float64)
+    grads = [gradient(prob, psi, d) for d in range(3)]
+    forces = []
+    for idx, chi, gam in atom_blocks(prob):
+        a = dv * (chi.T @ psi[idx, :])                     # np_J x Ns
+        f = np.zeros(3)
+        for d in range(3):
+            b = dv * (chi.T @ grads[d][idx, :])
+            f[d] = -2.0 * float(np.sum(gam[:, None] * occ[None, :] * a * b))
+        forces.append(f)
+    return np.array(forces).reshape(-1, 3)
+
+
+def nonlocal_energy(prob, psi: np.ndarray, occ: np.ndarray) -> float:
+    """E_nl = sum_n g_n sum_{J,a} gamma_Ja (dV chi_Ja^T psi_n)^2."""
+    dv = prob.h[0] * prob.h[1] * prob.h[2]
+    e = 0.0
+    for idx, chi, gam in atom_blocks(prob):
+        a = dv * (chi.T @ psi[idx, :])
+        e += float(np.sum(gam[:, None] * occ[None, :] * a * a))
+    return e

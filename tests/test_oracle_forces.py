@@ -1,0 +1,86 @@
+"""Pins for the oracle's nonlocal forces (Sec. 2: gradient of the orbitals, then the
+nonlocal projectors): textbook first-derivative weights and their moment conditions, the
+Fourier closed form of the FD gradient of plane waves, and forces equal to minus a central
+difference of the nonlocal energy when the atom (its sampled projectors) is displaced."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.forces import first_derivative_weights, gradient, nonlocal_energy, nonlocal_forces
+from tests.test_oracle_hamiltonian import bare_problem
+
+
+@pytest.mark.parametrize("order,ref", [(2, [0.5]), (4, [2 / 3, -1 / 12]), (6, [3 / 4, -3 / 20, 1 / 60]),
+                                       (8, [4 / 5, -1 / 5, 4 / 105, -1 / 280])])
+def test_textbook_weights(order, ref):
+    np.testing.assert_allclose(first_derivative_weights(order)[1:], ref, rtol=1e-14)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12])
+def test_moment_conditions(order):
+    c = first_derivative_weights(order)
+    r = order // 2
+    for k in range(1, 2 * r + 1):          # exact on polynomials up to degree 2r
+        s = sum(c[p] * (p ** k - (-p) ** k) for p in range(1, r + 1))
+        assert s == pytest.approx(1.0 if k == 1 else 0.0, abs=1e-12)
+
+
+def test_gradient_of_plane_waves_closed_form():
+    n, h, order = (12, 10, 14), (0.3, 0.25, 0.35), 12
+    prob = bare_problem(n, h, (0, 0, 0), order)
+    c = first_derivative_weights(order)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    coords = (x, y, z)
+    for d in range(3):
+        for k in (1, 3, n[d] // 2 - 1):
+            th = 2 * np.pi * k / n[d]
+            f = np.cos(th * coords[d]).reshape(-1, 1)
+            s = 2 * sum(c[p] * math.sin(p * th) for p in range(1, len(c)))
+            ref = (-s / h[d]) * np.sin(th * coords[d]).reshape(-1, 1)
+            np.testing.assert_allclose(gradient(prob, f, d), ref, atol=1e-12 / h[d])
+
+
+def _gaussian_atom(n, h, R, sigma=0.45):
+    """s + p Gaussian projectors of an atom at R sampled on the whole periodic grid (minimum image)."""
+    L = np.array(n) * np.array(h)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    r = [x.reshape(-1) * h[0], y.reshape(-1) * h[1], z.reshape(-1) * h[2]]
+    dr = [(r[d] - R[d] + 0.5 * L[d]) % L[d] - 0.5 * L[d] for d in range(3)]
+    g = np.exp(-(dr[0] ** 2 + dr[1] ** 2 + dr[2] ** 2) / (2 * sigma ** 2))
+    chi = np.stack([g, dr[0] / sigma * g, dr[1] / sigma * g, dr[2] / sigma * g], axis=1)
+    return np.arange(len(g)), chi, [0.7, -0.3, 0.45, 0.2]
+
+
+def test_forces_are_minus_energy_gradient():
+    n, h, order = (28, 26, 30), (0.2, 0.21, 0.19), 12
+    rng = np.random.default_rng(12)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ph = [2 * np.pi * x / n[0], 2 * np.pi * y / n[1], 2 * np.pi * z / n[2]]
+    ns = 3
+    psi = np.zeros((x.size, ns))
+    for j in range(ns):                     # band-limited orbitals (|k| <= 2 per direction)
+        f = np.zeros(x.shape)
+        for kx in range(-2, 3):
+            for ky in range(-2, 3):
+                for kz in range(-2, 3):
+                    a, b = rng.standard_normal(2)
+                    t = kx * ph[0] + ky * ph[1] + kz * ph[2]
+                    f += a * np.cos(t) + b * np.sin(t)
+        psi[:, j] = f.reshape(-1)
+    occ = np.array([2.0, 1.5, 0.5])
+    atoms = [np.array([2.31, 2.57, 2.93]), np.array([3.9, 1.2, 4.1])]
+
+    def problem(positions):
+        return bare_problem(n, h, (0, 0, 0), order, atoms=[_gaussian_atom(n, h, R) for R in positions])
+
+    F = nonlocal_forces(problem(atoms), psi, occ)
+    delta = 1e-4
+    for J in range(len(atoms)):
+        for d in range(3):
+            plus = [a.copy() for a in atoms]
+            minus = [a.copy() for a in atoms]
+            plus[J][d] += delta
+            minus[J][d] -= delta
+            fd = -(nonlocal_energy(problem(plus), psi, occ) - nonlocal_energy(problem(minus), psi, occ)) / (2 * delta)
+            assert F[J, d] == pytest.approx(fd, abs=1e-6 * np.abs(F).max())
