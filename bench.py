@@ -219,6 +219,30 @@ def lanczos_figures(cs, prob, cfg, precision: str, steps: int = 20):
     return {"steps": steps, "ms": ms, "theta": theta, "lam_nd": lam, "gershgorin_lam_hi": gersh}
 
 
+def forces_figures(cs, prob, cfg, precision: str):
+    """Nonlocal forces of the workload's Ns orbitals (outside the timed steps): time of one
+    call (three gradient passes, four projector gathers, the force sums)."""
+    import torch
+    prec = cs.FP64 if precision == "fp64" else cs.MIXED
+    ns = cfg.ns
+    h = cs.Handle(prob, precision=prec, max_ns=ns)
+    ws = torch.empty(h.chefsi_forces_workspace_bytes(ns), dtype=torch.uint8, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(cfg.x_seed + 2)
+    X = torch.randn((ns, prob.nd), generator=g, device="cuda",
+                    dtype=torch.float64 if prec == cs.FP64 else torch.float32)
+    occ = np.full(ns, 2.0)
+    h.chefsi_nonlocal_forces(X, ns, occ, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = h.chefsi_nonlocal_forces(X, ns, occ, ws)
+    ms = (time.perf_counter() - t0) * 1e3
+    h.close()
+    del ws, X
+    torch.cuda.empty_cache()
+    return {"ms": ms, "atoms": int(f.shape[0]), "orbitals": ns, "max_abs_force": float(np.abs(f).max())}
+
+
 def copy_gbs():
     """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes / time), the
     practical streaming ceiling the stencil's rate is also compared with."""
@@ -326,6 +350,7 @@ def main():
         del src, dst
 
     lz = lanczos_figures(cs, prob, cfg, precision)
+    fo = forces_figures(cs, prob, cfg, precision) if prob.n_atoms > 0 else None
     cgbs = copy_gbs()
     kern = main_run["kernels"]
     # the dominant kernel among those with a roofline (the FP64 dense stage and copies have none)
@@ -371,6 +396,7 @@ def main():
         "kernels": kern,
         "solve_ms": main_run["solve_ms"],
         "lanczos_lam_nd": lz,
+        "nonlocal_forces": fo,
     }
     if other is not None:
         out["compare"] = {

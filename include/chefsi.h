@@ -166,6 +166,23 @@ int chefsi_lanczos_workspace_bytes(const chefsi_handle_t* h, size_t* bytes);
 int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void* ws, size_t ws_bytes,
                          void* stream, double* lam_nd, double* theta, double* alpha_host, double* beta_host);
 
+/* Nonlocal (Kleinman-Bylander) part of the Hellmann-Feynman atomic forces, computed the
+ * way the paper reuses its filter kernels for forces (Sec. 2: the gradient operator on
+ * the orbitals, then the nonlocal projectors on the result):
+ *   F_J,d = -2 sum_n g_n sum_a gamma_Ja (dV chi_Ja^T psi_n) (dV chi_Ja^T d psi_n / dx_d),
+ * d/dx_d the central FD first derivative of the handle's order 2r (weights
+ * c_p = (-1)^(p+1) (r!)^2 / (p (r-p)! (r+p)!), periodic wrap or zero ghosts as the grid).
+ * X: ns orbitals psi_n on the device, Nd x ns column-major in the handle's storage type;
+ * occ_host: ns occupations g_n; forces_host: n_atoms x 3 doubles (atom-major), written
+ * after the stream is synchronised.  FP64 arithmetic throughout.  Forces add over
+ * orbitals, so a large block may be passed in column chunks and the results summed.
+ * ws: chefsi_forces_workspace_bytes(ns) bytes of device memory (an FP64 Nd x ns
+ * gradient block and the projector coefficients).  Errors: ERR_INVALID_ARG,
+ * ERR_WORKSPACE, ERR_HIP. */
+int chefsi_forces_workspace_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes);
+int chefsi_nonlocal_forces(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
+                           size_t ws_bytes, void* stream, double* forces_host);
+
 /* Y = H X for an Nd x ns block (Sec. 2.1: stencil + Veff + nonlocal).  X and Y
  * are distinct device blocks of the handle's element type. */
 int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns,

@@ -40,7 +40,7 @@ EXPORTS = (
     "chefsi_step", "chefsi_solve", "chefsi_refine_fp64", "chefsi_profile_enable",
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
     "chefsi_last_error", "chefsi_version", "chefsi_lanczos_workspace_bytes", "chefsi_lanczos_bound",
-    "chefsi_update_veff",
+    "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
 )
 
 
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
     lib.chefsi_update_veff.argtypes = [vp, pd, vp]
+    lib.chefsi_forces_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    lib.chefsi_nonlocal_forces.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
     lib.chefsi_lanczos_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_lanczos_bound.argtypes = [vp, vp, i32, vp, sz, vp, pd, pd, pd, pd]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
@@ -165,6 +167,7 @@ class Handle:
         self.h = h
         self.precision = precision
         self.nd = int(np.prod(problem.n))
+        self.n_atoms = int(len(problem.nproj))
         self.max_ns = int(max_ns)
 
     # -- helpers ---------------------------------------------------------------
@@ -208,6 +211,22 @@ class Handle:
         if v.size != self.nd:
             raise ValueError(f"Veff has {v.size} values, the grid {self.nd}")
         self._check(self._lib.chefsi_update_veff(self.h, v.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+
+    def chefsi_forces_workspace_bytes(self, ns: int) -> int:
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_forces_workspace_bytes(self.h, int(ns), C.byref(b)))
+        return int(b.value)
+
+    def chefsi_nonlocal_forces(self, X, ns, occ, ws, ws_bytes=None, stream=None) -> np.ndarray:
+        """(n_atoms, 3) nonlocal forces of the ns orbitals X with occupations occ."""
+        g = np.ascontiguousarray(occ, dtype=np.float64).reshape(-1)
+        if g.size != int(ns):
+            raise ValueError("need one occupation per orbital")
+        f = np.zeros((self.n_atoms, 3))
+        self._check(self._lib.chefsi_nonlocal_forces(self.h, _ptr(X), int(ns), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                                     _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream),
+                                                     f.ctypes.data_as(C.POINTER(C.c_double))))
+        return f
 
     def chefsi_lanczos_workspace_bytes(self) -> int:
         b = C.c_size_t()

@@ -1395,9 +1395,132 @@ void lanczos_impl(chefsi_handle* h, const TV* v0, int steps, void* ws, const LzL
   }
 }
 
+// ---------------------------------------------------------------------------
+// Nonlocal forces.  Workspace: one gradient block (FP64, Nd x ns), the two coefficient
+// blocks (np_tot x ns FP64), dV per projector column, occupations, forces.
+// ---------------------------------------------------------------------------
+struct FoLayout {
+  size_t grad = 0, alpha = 0, beta = 0, dvc = 0, occ = 0, forces = 0, total = 0;
+};
+
+FoLayout forces_layout(const chefsi_handle* h, int ns) {
+  FoLayout L;
+  const size_t np = (size_t)std::max(1, h->np_tot);
+  size_t off = 0;
+  L.grad = off;
+  off += align256((size_t)h->nd * ns * 8);
+  L.alpha = off;
+  off += align256(np * ns * 8);
+  L.beta = off;
+  off += align256(np * ns * 8);
+  L.dvc = off;
+  off += align256(np * 8);
+  L.occ = off;
+  off += align256((size_t)ns * 8);
+  L.forces = off;
+  off += align256((size_t)std::max(1, h->n_atoms) * 3 * 8);
+  L.total = off;
+  return L;
+}
+
+// Central first-derivative weights of order 2r: c_p = (-1)^(p+1) (r!)^2 / (p (r-p)! (r+p)!).
+std::vector<double> first_derivative_weights(int r) {
+  std::vector<double> c(r + 1, 0.0);
+  auto fact = [](int k) {
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+  };
+  for (int p = 1; p <= r; ++p)
+    c[p] = ((p % 2) ? 1.0 : -1.0) * fact(r) * fact(r) / (p * fact(r - p) * fact(r + p));
+  return c;
+}
+
+template <typename TV>
+void forces_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, void* ws, const FoLayout& L,
+                 hipStream_t s, double* forces_host) {
+  const std::vector<double> dvc(std::max(1, h->np_tot), h->dv);
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.dvc), dvc.data(), dvc.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.occ), occ_host, (size_t)ns * 8, hipMemcpyHostToDevice, s));
+  double* alpha = at<double>(ws, L.alpha);
+  double* beta = at<double>(ws, L.beta);
+  double* grad = at<double>(ws, L.grad);
+  const double* dv = at<double>(ws, L.dvc);
+  HIP_TRY((launch_nl_project<TV, double>(nl_args<TV, double>(h, X, ns, h->chi64, dv, alpha), s)));
+  const std::vector<double> c = first_derivative_weights(h->radius);
+  for (int d = 0; d < 3; ++d) {
+    GradArgs<TV> g{};
+    g.x = X;
+    g.out = grad;
+    g.nd = h->nd;
+    g.nx = h->n[0];
+    g.ny = h->n[1];
+    g.nz = h->n[2];
+    g.dir = d;
+    g.r = h->radius;
+    g.periodic = h->bc[d] == 0 ? 1 : 0;
+    for (int p = 0; p <= h->radius; ++p) g.c[p] = c[p];
+    g.inv_h = 1.0 / h->h[d];
+    HIP_TRY(launch_grad<TV>(g, ns, s));
+    HIP_TRY((launch_nl_project<double, double>(nl_args<double, double>(h, grad, ns, h->chi64, dv, beta), s)));
+    ForceArgs f{};
+    f.alpha = alpha;
+    f.beta = beta;
+    f.occ = at<double>(ws, L.occ);
+    f.gdv = h->gdv64;
+    f.nproj = h->nproj;
+    f.poff = h->poff;
+    f.dv = h->dv;
+    f.n_atoms = h->n_atoms;
+    f.np_tot = h->np_tot;
+    f.ns = ns;
+    f.dir = d;
+    f.forces = at<double>(ws, L.forces);
+    HIP_TRY(launch_forces(f, s));
+  }
+  double* pin = nullptr;
+  const size_t fb = (size_t)h->n_atoms * 3 * 8;
+  HIP_TRY(hipHostMalloc((void**)&pin, fb, hipHostMallocDefault));
+  hipError_t e = hipMemcpyAsync(pin, at<double>(ws, L.forces), fb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) std::memcpy(forces_host, pin, fb);
+  (void)hipHostFree(pin);
+  HIP_TRY(e);
+}
+
 }  // namespace
 
 extern "C" {
+
+int chefsi_forces_workspace_bytes(const chefsi_handle_t* hc, int32_t ns, size_t* bytes) {
+  chefsi_handle* h = const_cast<chefsi_handle*>(hc);
+  return guarded(h, [&] {
+    check(bytes != nullptr, "bytes is NULL");
+    check_ns(h, ns);
+    *bytes = forces_layout(h, ns).total;
+  });
+}
+
+int chefsi_nonlocal_forces(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
+                           size_t ws_bytes, void* stream, double* forces_host) {
+  return guarded(h, [&] {
+    check(X != nullptr && occ_host != nullptr && forces_host != nullptr, "X, occ and forces must not be NULL");
+    check_ns(h, ns);
+    for (int i = 0; i < ns; ++i) check(std::isfinite(occ_host[i]), "occupations must be finite");
+    if (h->n_atoms == 0 || h->np_tot == 0) {
+      std::fill(forces_host, forces_host + 3 * (size_t)h->n_atoms, 0.0);
+      return;
+    }
+    check(ws != nullptr, "ws is NULL");
+    const FoLayout L = forces_layout(h, ns);
+    if (ws_bytes < L.total) throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_forces_workspace_bytes"};
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      forces_impl<double>(h, (const double*)X, ns, occ_host, ws, L, s, forces_host);
+    else
+      forces_impl<float>(h, (const float*)X, ns, occ_host, ws, L, s, forces_host);
+  });
+}
 
 int chefsi_lanczos_workspace_bytes(const chefsi_handle_t* hc, size_t* bytes) {
   chefsi_handle* h = const_cast<chefsi_handle*>(hc);

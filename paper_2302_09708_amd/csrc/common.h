@@ -176,6 +176,37 @@ hipError_t launch_rotate_bf16x3(const float* X, const double* Z, void* zsplit, f
                                 hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Nonlocal forces: out = d x / d x_dir (central FD, c[1..r], periodic or zero ghosts),
+// then forces[J*3 + dir] = -2 sum_k (gdv[q]/dv) sum_v occ[v] alpha[v*np+q] beta[v*np+q].
+// ---------------------------------------------------------------------------
+template <typename TV>
+struct GradArgs {
+  const TV* x;
+  double* out;
+  int64_t nd;
+  int nx, ny, nz;
+  int dir, r, periodic;
+  double c[kMaxRadius + 1];
+  double inv_h;
+};
+
+struct ForceArgs {
+  const double* alpha;
+  const double* beta;
+  const double* occ;
+  const double* gdv;
+  const int* nproj;
+  const int* poff;
+  double dv;
+  int n_atoms, np_tot, ns, dir;
+  double* forces;
+};
+
+template <typename TV>
+hipError_t launch_grad(const GradArgs<TV>& a, int ns, hipStream_t s);
+hipError_t launch_forces(const ForceArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Lanczos vector kernels (fixed grid of kVecBlocks x kVecThreads, fixed-order sums).
 // dot:   w -= beta vp (vp may be null); out[0] = v . w
 // norm:  w -= alpha v (v may be null);  out[0] = w . w
