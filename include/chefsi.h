@@ -183,6 +183,15 @@ int chefsi_forces_workspace_bytes(const chefsi_handle_t* h, int32_t ns, size_t* 
 int chefsi_nonlocal_forces(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
                            size_t ws_bytes, void* stream, double* forces_host);
 
+/* Electronic kinetic-energy component of the stress from the same FD gradient of the
+ * orbitals (Sec. 2 names this reuse of the gradient for the stresses):
+ *   sigma_ab = -(1 / Omega) sum_n g_n dV sum_i (d psi_n/dx_a)(i) (d psi_n/dx_b)(i),
+ * Omega = Nd dV, in Ha / bohr^3.  X, occ_host, ws as chefsi_nonlocal_forces (the same
+ * workspace size); stress_host: 9 doubles, row-major 3 x 3 (symmetric), written after the
+ * stream is synchronised.  Fixed-order sums (bitwise reproducible).  Errors as above. */
+int chefsi_kinetic_stress(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
+                          size_t ws_bytes, void* stream, double* stress_host);
+
 /* Y = H X for an Nd x ns block (Sec. 2.1: stencil + Veff + nonlocal).  X and Y
  * are distinct device blocks of the handle's element type. */
 int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns,

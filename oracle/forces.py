@@ -76,3 +76,21 @@ def nonlocal_energy(prob, psi: np.ndarray, occ: np.ndarray) -> float:
         a = dv * (chi.T @ psi[idx, :])
         e += float(np.sum(gam[:, None] * occ[None, :] * a * a))
     return e
+
+
+def kinetic_stress(prob, psi: np.ndarray, occ: np.ndarray) -> np.ndarray:
+    """Electronic kinetic-energy component of the stress (3 x 3, Ha / bohr^3) from the FD
+    gradient of the orbitals (Sec. 2 reuses that gradient for it):
+
+        sigma_ab = -(1 / Omega) sum_n g_n dV sum_i (d psi_n / dx_a)(i) (d psi_n / dx_b)(i),
+
+    Omega = Nd dV the cell volume; real orbitals."""
+    dv = prob.h[0] * prob.h[1] * prob.h[2]
+    psi = np.asarray(psi, dtype=np.float64)
+    omega = psi.shape[0] * dv
+    g = [gradient(prob, psi, d) for d in range(3)]
+    s = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            s[a, b] = -dv / omega * float(np.sum(occ[None, :] * g[a] * g[b]))
+    return s

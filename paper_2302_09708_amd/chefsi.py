@@ -41,6 +41,7 @@ EXPORTS = (
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
     "chefsi_last_error", "chefsi_version", "chefsi_lanczos_workspace_bytes", "chefsi_lanczos_bound",
     "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
+    "chefsi_kinetic_stress",
 )
 
 
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.chefsi_update_veff.argtypes = [vp, pd, vp]
     lib.chefsi_forces_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_nonlocal_forces.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
+    lib.chefsi_kinetic_stress.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
     lib.chefsi_lanczos_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_lanczos_bound.argtypes = [vp, vp, i32, vp, sz, vp, pd, pd, pd, pd]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
@@ -227,6 +229,17 @@ class Handle:
                                                      _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream),
                                                      f.ctypes.data_as(C.POINTER(C.c_double))))
         return f
+
+    def chefsi_kinetic_stress(self, X, ns, occ, ws, ws_bytes=None, stream=None) -> np.ndarray:
+        """3 x 3 kinetic stress of the ns orbitals X with occupations occ."""
+        g = np.ascontiguousarray(occ, dtype=np.float64).reshape(-1)
+        if g.size != int(ns):
+            raise ValueError("need one occupation per orbital")
+        out = np.zeros(9)
+        self._check(self._lib.chefsi_kinetic_stress(self.h, _ptr(X), int(ns), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                                    _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream),
+                                                    out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(3, 3)
 
     def chefsi_lanczos_workspace_bytes(self) -> int:
         b = C.c_size_t()

@@ -1400,7 +1400,7 @@ void lanczos_impl(chefsi_handle* h, const TV* v0, int steps, void* ws, const LzL
 // blocks (np_tot x ns FP64), dV per projector column, occupations, forces.
 // ---------------------------------------------------------------------------
 struct FoLayout {
-  size_t grad = 0, alpha = 0, beta = 0, dvc = 0, occ = 0, forces = 0, total = 0;
+  size_t grad = 0, alpha = 0, beta = 0, dvc = 0, occ = 0, forces = 0, spart = 0, total = 0;
 };
 
 FoLayout forces_layout(const chefsi_handle* h, int ns) {
@@ -1419,6 +1419,8 @@ FoLayout forces_layout(const chefsi_handle* h, int ns) {
   off += align256((size_t)ns * 8);
   L.forces = off;
   off += align256((size_t)std::max(1, h->n_atoms) * 3 * 8);
+  L.spart = off;  // stress block sums (kVecBlocks x 6) and the six totals
+  off += align256(((size_t)kVecBlocks * 6 + 8) * 8);
   L.total = off;
   return L;
 }
@@ -1488,9 +1490,62 @@ void forces_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, 
   HIP_TRY(e);
 }
 
+template <typename TV>
+void kinetic_stress_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, void* ws, const FoLayout& L,
+                         hipStream_t s, double* stress_host) {
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.occ), occ_host, (size_t)ns * 8, hipMemcpyHostToDevice, s));
+  const std::vector<double> c = first_derivative_weights(h->radius);
+  StressArgs<TV> a{};
+  a.x = X;
+  a.occ = at<double>(ws, L.occ);
+  a.nd = h->nd;
+  a.ns = ns;
+  a.nx = h->n[0];
+  a.ny = h->n[1];
+  a.nz = h->n[2];
+  a.r = h->radius;
+  for (int d = 0; d < 3; ++d) {
+    a.periodic[d] = h->bc[d] == 0 ? 1 : 0;
+    a.inv_h[d] = 1.0 / h->h[d];
+  }
+  for (int p = 0; p <= h->radius; ++p) a.c[p] = c[p];
+  a.partial = at<double>(ws, L.spart);
+  a.out = a.partial + (size_t)kVecBlocks * 6;
+  HIP_TRY(launch_stress_sums<TV>(a, s));
+  double* pin = h->pinned;  // max_ns + 8 doubles; six needed
+  double sums[6];
+  HIP_TRY(hipMemcpyAsync(pin, a.out, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(sums, pin, sizeof(sums));
+  // sigma_ab = -(dV / Omega) sum = -(1 / Nd) sum, Omega = Nd dV
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int k = 0; k < 6; ++k) {
+    const double v = -sums[k] / (double)h->nd;
+    stress_host[ia[k] * 3 + ib[k]] = v;
+    stress_host[ib[k] * 3 + ia[k]] = v;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+int chefsi_kinetic_stress(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
+                          size_t ws_bytes, void* stream, double* stress_host) {
+  return guarded(h, [&] {
+    check(X != nullptr && occ_host != nullptr && stress_host != nullptr && ws != nullptr,
+          "X, occ, stress and ws must not be NULL");
+    check_ns(h, ns);
+    for (int i = 0; i < ns; ++i) check(std::isfinite(occ_host[i]), "occupations must be finite");
+    const FoLayout L = forces_layout(h, ns);
+    if (ws_bytes < L.total) throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_forces_workspace_bytes"};
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      kinetic_stress_impl<double>(h, (const double*)X, ns, occ_host, ws, L, s, stress_host);
+    else
+      kinetic_stress_impl<float>(h, (const float*)X, ns, occ_host, ws, L, s, stress_host);
+  });
+}
 
 int chefsi_forces_workspace_bytes(const chefsi_handle_t* hc, int32_t ns, size_t* bytes) {
   chefsi_handle* h = const_cast<chefsi_handle*>(hc);

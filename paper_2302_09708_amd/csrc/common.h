@@ -10,6 +10,8 @@
 namespace chefsi {
 
 constexpr int kMaxRadius = 6;  // finite-difference order up to 12
+constexpr int kVecThreads = 256;   // fixed-grid reductions (Lanczos sums, stress sums)
+constexpr int kVecBlocks = 1024;
 constexpr int kHxMaxThreads = 512;  // widest supported x row (one thread per x point)
 // stencil threads per block for PY rows per thread (1024 keeps 128 VGPRs per lane, 512 keeps 256)
 constexpr int hx_max_threads(int py) { return py == 1 ? 1024 : 512; }
@@ -204,6 +206,25 @@ struct ForceArgs {
 
 template <typename TV>
 hipError_t launch_grad(const GradArgs<TV>& a, int ns, hipStream_t s);
+
+// Kinetic stress sums: out[0..5] = sum_v occ[v] sum_i g_a g_b for ab = xx, yy, zz, xy, xz,
+// yz (g = FD gradient of orbital v); partial: kVecBlocks * 6 doubles of scratch.
+template <typename TV>
+struct StressArgs {
+  const TV* x;
+  const double* occ;
+  int64_t nd;
+  int ns;
+  int nx, ny, nz, r;
+  int periodic[3];
+  double c[kMaxRadius + 1];
+  double inv_h[3];
+  double* partial;
+  double* out;
+};
+
+template <typename TV>
+hipError_t launch_stress_sums(const StressArgs<TV>& a, hipStream_t s);
 hipError_t launch_forces(const ForceArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -213,8 +234,6 @@ hipError_t launch_forces(const ForceArgs& a, hipStream_t s);
 // scale: out = TV(w * inv);  widen: w = double(x)
 // partial: kVecBlocks doubles of scratch.
 // ---------------------------------------------------------------------------
-constexpr int kVecThreads = 256;
-constexpr int kVecBlocks = 1024;
 
 template <typename TV>
 hipError_t launch_lanczos_dot(double* w, const TV* v, const TV* vp, double beta, int64_t n, double* partial,

@@ -87,3 +87,25 @@ def test_no_atoms_and_errors(cs):
         h.chefsi_nonlocal_forces(Xd, 4, np.array([1.0, np.inf, 1.0, 1.0]), ws)
     assert np.array_equal(h.chefsi_nonlocal_forces(Xd, 4, np.ones(4), ws), np.zeros((prob.n_atoms, 3)))
     h.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_kinetic_stress_matches_oracle(cs, case):
+    from oracle.forces import kinetic_stress
+    prob = _problem(case)
+    ns = case[2]
+    X = inputs.initial_block(prob.nd, ns, 3002).T
+    occ = np.linspace(2.0, 0.5, ns)
+    ref = kinetic_stress(prob, X, occ)
+    for precision, tol in ((cs.FP64, 1e-12), (cs.MIXED, 1e-6)):
+        h = cs.Handle(prob, precision=precision, max_ns=ns)
+        ws = torch.empty(h.chefsi_forces_workspace_bytes(ns), dtype=torch.uint8, device="cuda")
+        dt = torch.float64 if precision == cs.FP64 else torch.float32
+        Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(device="cuda", dtype=dt)
+        got = h.chefsi_kinetic_stress(Xd, ns, occ, ws)
+        again = h.chefsi_kinetic_stress(Xd, ns, occ, ws)
+        h.close()
+        assert np.array_equal(got, got.T) and np.array_equal(got, again)
+        xr = X if precision == cs.FP64 else X.astype(np.float32).astype(np.float64)
+        r = ref if precision == cs.FP64 else kinetic_stress(prob, xr, occ)
+        assert np.abs(got - r).max() <= tol * np.abs(r).max()

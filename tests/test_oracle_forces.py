@@ -84,3 +84,24 @@ def test_forces_are_minus_energy_gradient():
             minus[J][d] -= delta
             fd = -(nonlocal_energy(problem(plus), psi, occ) - nonlocal_energy(problem(minus), psi, occ)) / (2 * delta)
             assert F[J, d] == pytest.approx(fd, abs=1e-6 * np.abs(F).max())
+
+
+def test_kinetic_stress_of_plane_waves():
+    """sigma_ab of cos(k.r) / sqrt(Nd dV) with occupation g: -(g / Omega) s_a s_b / 2 (the FD
+    gradient's symbol s_d = 2 sum_p c_p sin(p theta_d) / h_d), zero off the wave's axes."""
+    from oracle.forces import kinetic_stress
+    n, h, order = (12, 10, 14), (0.3, 0.25, 0.35), 12
+    prob = bare_problem(n, h, (0, 0, 0), order)
+    c = first_derivative_weights(order)
+    dv = h[0] * h[1] * h[2]
+    omega = prob.nd * dv
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    k = (2, 3, 0)
+    th = [2 * np.pi * k[0] / n[0], 2 * np.pi * k[1] / n[1], 2 * np.pi * k[2] / n[2]]
+    psi = (np.cos(th[0] * x + th[1] * y + th[2] * z) / np.sqrt(prob.nd * dv)).reshape(-1, 1)
+    s_sym = [2 * sum(c[p] * math.sin(p * th[d]) for p in range(1, len(c))) / h[d] for d in range(3)]
+    g = 1.7
+    ref = -(g / omega) * 0.5 * np.outer(s_sym, s_sym)
+    got = kinetic_stress(prob, psi, np.array([g]))
+    np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max())
+    assert np.array_equal(got, got.T)
