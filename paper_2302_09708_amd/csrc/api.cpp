@@ -167,12 +167,42 @@ BlasGram plan_blas_gram(int64_t nd, int ns) {
   return b;
 }
 
+// FP64 products of the FP32 block of a mixed handle (its FP64 Rayleigh-Ritz pass): the
+// block is widened to FP64 one row panel at a time and each panel goes to rocBLAS dgemm.
+// A panel is `splits` chunks of kc rows; the Gram partials of chunk q of every panel
+// accumulate into partial q in panel order, then the partials are summed in a fixed
+// order.  A panel holds at most kPanelBytes and a quarter of the rows, so it fits beside
+// the FP32 result in the upper half of the FP64 scratch block.
+constexpr int64_t kPanelBytes = (int64_t)512 << 20;
+
+struct PanelPlan {
+  int splits = 1;
+  int64_t kc = 0, rows = 0;
+  size_t part_bytes = 0;   // one set of Gram partials
+  size_t panel_bytes = 0;  // one rows x ns FP64 panel
+};
+
+PanelPlan plan_panels(int64_t nd, int ns) {
+  PanelPlan p;
+  const int64_t tiles = ((int64_t)(ns + 127) / 128) * ((ns + 127) / 128);
+  const int64_t budget = std::max<int64_t>(1, std::min<int64_t>(kPanelBytes / ((int64_t)ns * 8), nd / 4));
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>({128, 4096 / tiles, budget / 2048}));
+  const int64_t kc = std::max<int64_t>(1, budget / splits);
+  p.splits = (int)splits;
+  p.kc = kc;
+  p.rows = splits * kc;
+  p.part_bytes = (size_t)splits * ns * ns * sizeof(double);
+  p.panel_bytes = (size_t)p.rows * ns * sizeof(double);
+  return p;
+}
+
 struct WsLayout {
-  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, sc = 0, info = 0, partial = 0, zsplit = 0, solver = 0,
-         total = 0;
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, sc = 0, info = 0, partial = 0, zsplit = 0, panel = 0,
+         panel_out = 0, solver = 0, total = 0;
   size_t bufB_bytes = 0, solver_bytes = 0;
   GramPlan gram;
-  BlasGram bgram;  // FP64 handles: Gram products of FP64 blocks
+  BlasGram bgram;   // FP64 handles: Gram products of FP64 blocks
+  PanelPlan pan;    // mixed handles: FP64 products of the FP32 block
 };
 
 // status words in the pinned staging buffer, after max_ns doubles
@@ -219,6 +249,17 @@ size_t solver_workspace(chefsi_handle* h, int ns) {
                                     (rocblas_int)b.kc, &one, nullptr, (rocblas_int)h->nd, b.kc, nullptr,
                                     (rocblas_int)h->nd, b.kc, &one, nullptr, ns, (rocblas_stride)ns * ns, b.splits);
     });
+  } else {
+    const PanelPlan p = plan_panels(h->nd, ns);
+    query([&] {
+      rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                                    (rocblas_int)p.kc, &one, nullptr, (rocblas_int)p.rows, p.kc, nullptr,
+                                    (rocblas_int)h->nd, p.kc, &one, nullptr, ns, (rocblas_stride)ns * ns, p.splits);
+    });
+    query([&] {
+      rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)p.rows, ns, ns, &one,
+                    nullptr, (rocblas_int)p.rows, nullptr, ns, &one, nullptr, (rocblas_int)p.rows);
+    });
   }
   if ((int64_t)h->nd * ns < ((int64_t)1 << 31))
     query([&] {
@@ -252,10 +293,23 @@ WsLayout layout(chefsi_handle* h, int ns) {
   off += 256;
   L.gram = plan_gram(h->nd, ns);
   L.bgram = plan_blas_gram(h->nd, ns);
+  L.pan = plan_panels(h->nd, ns);
   L.partial = off;
-  off += align256(std::max(L.gram.partial_bytes, h->precision == CHEFSI_FP64 ? L.bgram.bytes : (size_t)0));
+  off += align256(std::max(L.gram.partial_bytes,
+                           h->precision == CHEFSI_FP64 ? L.bgram.bytes : 2 * L.pan.part_bytes));
   L.zsplit = off;
   if (h->precision == CHEFSI_MIXED) off += align256(zsplit_bytes(ns));
+  L.panel = off;
+  if (h->precision == CHEFSI_MIXED) {
+    off += align256(L.pan.panel_bytes);
+    // the rotation's FP64 result panel: above the FP32 result in the FP64 scratch block
+    // (it fits there unless the grid is tiny), else a region of its own
+    L.panel_out = L.bufB + align256((size_t)h->nd * ns * 4);
+    if (L.panel_out + L.pan.panel_bytes > L.bufB + align256(L.bufB_bytes)) {
+      L.panel_out = off;
+      off += align256(L.pan.panel_bytes);
+    }
+  }
   L.solver = off;
   L.solver_bytes = solver_workspace(h, ns);
   off += align256(std::max<size_t>(L.solver_bytes, 256));
@@ -515,6 +569,76 @@ void blas_gram(chefsi_handle* h, const double* X, const double* Y, int ns, const
   }
 }
 
+// Hs = X^T Y and Ms = X^T X with FP64 arithmetic for the FP32 block X of a mixed handle
+// (Y = H X in FP64): each row panel of X is widened once and feeds both rocBLAS products.
+// Every FP32 value is exact in FP64, so this is the FP64 product of the stored block.
+void panel_gram(chefsi_handle* h, const float* X, const double* Y, int ns, const WsLayout& L, void* ws, double* Hs,
+                double* Ms, hipStream_t s) {
+  const PanelPlan& p = L.pan;
+  double* W = at<double>(ws, L.panel);
+  double* partH = at<double>(ws, L.partial);
+  double* partM = partH + (size_t)p.splits * ns * ns;
+  const double one = 1.0, zero = 0.0;
+  const rocblas_int ldw = (rocblas_int)p.rows, ldy = (rocblas_int)h->nd;
+  const rocblas_stride pst = (rocblas_stride)ns * ns;
+  {
+    ProfScope ps(h, P_GRAM, s);
+    BLAS_TRY(rocblas_set_stream(h->blas, s));
+    BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+    for (int64_t r0 = 0; r0 < h->nd; r0 += p.rows) {
+      // the first panel is whole (rows <= nd) and sets every partial; later panels add
+      const int64_t r = std::min(p.rows, h->nd - r0);
+      const double* beta = r0 == 0 ? &zero : &one;
+      HIP_TRY(launch_widen_rows(X + r0, h->nd, r, ns, W, p.rows, s));
+      const int64_t nfull = r / p.kc, tail = r - nfull * p.kc;
+      if (nfull > 0) {
+        BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                                               (rocblas_int)p.kc, &one, W, ldw, p.kc, Y + r0, ldy, p.kc, beta, partH,
+                                               ns, pst, (rocblas_int)nfull));
+        BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                                               (rocblas_int)p.kc, &one, W, ldw, p.kc, W, ldw, p.kc, beta, partM, ns,
+                                               pst, (rocblas_int)nfull));
+      }
+      if (tail > 0) {  // only in a last, partial panel: nfull < splits and r0 > 0
+        const int64_t k0 = nfull * p.kc;
+        BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                               (rocblas_int)tail, &one, W + k0, ldw, Y + r0 + k0, ldy, &one, partH + nfull * pst,
+                               ns));
+        BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
+                               (rocblas_int)tail, &one, W + k0, ldw, W + k0, ldw, &one, partM + nfull * pst, ns));
+      }
+    }
+    ps.done();
+  }
+  {
+    ProfScope ps(h, P_REDUCE, s);
+    HIP_TRY(launch_sum_partials(partH, p.splits, ns, Hs, s));
+    HIP_TRY(launch_sum_partials(partM, p.splits, ns, Ms, s));
+    ps.done();
+  }
+}
+
+// O = X Z with FP64 arithmetic for the FP32 block X of a mixed handle, rounded once to
+// FP32: per row panel, widen, rocBLAS dgemm into the FP64 result panel, narrow into O.
+void panel_rotate(chefsi_handle* h, const float* X, const double* Z, float* O, int ns, const WsLayout& L, void* ws,
+                  hipStream_t s) {
+  ProfScope ps(h, P_ROT, s);
+  const PanelPlan& p = L.pan;
+  double* W = at<double>(ws, L.panel);
+  double* P = at<double>(ws, L.panel_out);
+  const double one = 1.0, zero = 0.0;
+  BLAS_TRY(rocblas_set_stream(h->blas, s));
+  BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+  for (int64_t r0 = 0; r0 < h->nd; r0 += p.rows) {
+    const int64_t r = std::min(p.rows, h->nd - r0);
+    HIP_TRY(launch_widen_rows(X + r0, h->nd, r, ns, W, p.rows, s));
+    BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)r, ns, ns, &one, W,
+                           (rocblas_int)p.rows, Z, ns, &zero, P, (rocblas_int)p.rows));
+    HIP_TRY(launch_narrow_rows(P, p.rows, r, ns, O + r0, h->nd, s));
+  }
+  ps.done();
+}
+
 // Hs = X^T Y, Ms = X^T X (full symmetric, FP64), via split-K partial tiles.
 template <typename TX, typename TY>
 void gram_pair(chefsi_handle* h, const TX* X, const TY* Y, int ns, const WsLayout& L, void* ws, double* Hs,
@@ -641,6 +765,12 @@ void copy_block(chefsi_handle* h, T* dst, const T* src, int ns, hipStream_t s) {
 template <typename T>
 void rotate_into(chefsi_handle* h, const T* X, const double* Z, T* O, int ns, hipStream_t s, Gemm g, void* ws,
                  const WsLayout& L) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (g == Gemm::F64) {
+      panel_rotate(h, X, Z, O, ns, L, ws, s);
+      return;
+    }
+  }
   ProfScope ps(h, P_ROT, s);
   if constexpr (std::is_same<T, float>::value) {
     if (g == Gemm::BF16X3) {
@@ -728,10 +858,16 @@ void refine_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, d
   double* Ms = at<double>(ws, L.ms);
   double* D = at<double>(ws, L.d);
   apply_fused<T, double, double>(h, X, nullptr, HX, ns, 1.0, 0.0, 0.0, alpha, s);
-  gram_pair<T, double>(h, X, HX, ns, L, ws, Hs, Ms, s, Gemm::F64);
-  dense_eig(h, Hs, Ms, D, ns, L, ws, s);
   T* B = at<T>(ws, L.bufB);
-  rotate_into<T>(h, X, Hs, B, ns, s, Gemm::F64, ws, L);
+  if constexpr (std::is_same<T, float>::value) {
+    panel_gram(h, X, HX, ns, L, ws, Hs, Ms, s);
+    dense_eig(h, Hs, Ms, D, ns, L, ws, s);
+    panel_rotate(h, X, Hs, B, ns, L, ws, s);
+  } else {
+    gram_pair<T, double>(h, X, HX, ns, L, ws, Hs, Ms, s, Gemm::F64);
+    dense_eig(h, Hs, Ms, D, ns, L, ws, s);
+    rotate_into<T>(h, X, Hs, B, ns, s, Gemm::F64, ws, L);
+  }
   copy_block<T>(h, X, B, ns, s);
   ritz_to_host(h, D, ns, ritz_host, ws, L, s);
 }

@@ -158,6 +158,14 @@ hipError_t launch_gram_reduce(const double* partial, const GramPlan& p, int ns, 
 // triangle read, summed in a fixed order).
 hipError_t launch_sum_partials(const double* P, int nparts, int ns, double* C, hipStream_t s);
 
+// Row panels of an FP32 block for the FP64 library products of a mixed handle's
+// refinement: W(i, c) = double(X(i, c)) and O(i, c) = float(P(i, c)), i < r, c < ns
+// (X, O: ld ldx; W, P: ld ldw).
+hipError_t launch_widen_rows(const float* X, int64_t ldx, int64_t r, int ns, double* W, int64_t ldw,
+                             hipStream_t s);
+hipError_t launch_narrow_rows(const double* P, int64_t ldw, int64_t r, int ns, float* O, int64_t ldx,
+                              hipStream_t s);
+
 // Diagonal scaling of the pencil (Hs, Ms) by sc_i = Ms_ii^-1/2 (sc: ns doubles, written),
 // and the matching back-transformation Z(i, j) <- sc_i Z(i, j).
 hipError_t launch_pencil_scale(double* Hs, double* Ms, double* sc, int ns, hipStream_t s);

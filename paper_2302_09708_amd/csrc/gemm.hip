@@ -178,6 +178,44 @@ hipError_t launch_sum_partials(const double* P, int nparts, int ns, double* C, h
   return hipGetLastError();
 }
 
+// Row panels of an FP32 block for FP64 library products: W(i, c) = double(X(i, c)) and
+// O(i, c) = float(P(i, c)) for i < r, c < ns (X, O: ld ldx; W, P: ld ldw).  Columns are
+// dealt over grid.y, rows over grid.x; the FP64 -> FP32 step rounds to nearest.
+__global__ __launch_bounds__(256) void widen_rows_kernel(const float* __restrict__ X, int64_t ldx, int64_t r,
+                                                         int ns, double* __restrict__ W, int64_t ldw) {
+  for (int c = blockIdx.y; c < ns; c += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < r; i += (int64_t)gridDim.x * 256)
+      W[c * ldw + i] = double(X[c * ldx + i]);
+}
+
+__global__ __launch_bounds__(256) void narrow_rows_kernel(const double* __restrict__ P, int64_t ldw, int64_t r,
+                                                          int ns, float* __restrict__ O, int64_t ldx) {
+  for (int c = blockIdx.y; c < ns; c += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < r; i += (int64_t)gridDim.x * 256)
+      O[c * ldx + i] = float(P[c * ldw + i]);
+}
+
+namespace {
+dim3 panel_grid(int64_t r, int ns) {
+  const int64_t bx = std::min<int64_t>((r + 255) / 256, 64);
+  return dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)std::min(std::max(ns, 1), 1024));
+}
+}  // namespace
+
+hipError_t launch_widen_rows(const float* X, int64_t ldx, int64_t r, int ns, double* W, int64_t ldw,
+                             hipStream_t s) {
+  if (r <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_rows_kernel, panel_grid(r, ns), dim3(256), 0, s, X, ldx, r, ns, W, ldw);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow_rows(const double* P, int64_t ldw, int64_t r, int ns, float* O, int64_t ldx,
+                              hipStream_t s) {
+  if (r <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(narrow_rows_kernel, panel_grid(r, ns), dim3(256), 0, s, P, ldw, r, ns, O, ldx);
+  return hipGetLastError();
+}
+
 GramPlan plan_gram(int64_t nd, int ns) {
   GramPlan p;
   p.tile = kTile;

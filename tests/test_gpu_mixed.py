@@ -161,9 +161,12 @@ def test_mixed_step_ritz_and_determinism(cs, cfg1_ref):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def test_refine_degree0_is_fp64_rayleigh_ritz(cs):
-    """degree 0: Rayleigh-Ritz of the stored block with FP64 arithmetic (no filter)."""
-    prob = inputs.small_problem(n=(14, 13, 12), n_atoms=3, nproj_per_atom=4, seed=3)
+@pytest.mark.parametrize("n", [(14, 13, 12), (26, 25, 27)])
+def test_refine_degree0_is_fp64_rayleigh_ritz(cs, n):
+    """degree 0: Rayleigh-Ritz of the stored block with FP64 arithmetic (no filter).  The
+    FP32 block goes through FP64 row panels: 2184 points are four whole panels, 17550
+    points are four panels of two K chunks and a last panel of six rows."""
+    prob = inputs.small_problem(n=n, n_atoms=3, nproj_per_atom=4, seed=3)
     ns = 24
     X = _f32(np.random.default_rng(2).standard_normal((prob.nd, ns)))
     hs, ms = oc.project(prob, X)
