@@ -104,12 +104,24 @@ def cpu_baseline(prob, cfg, ns_cols: int):
     }
 
 
+def gram_block_starts(ns: int) -> list:
+    """Column blocks of the library's upper-triangle FP64 Gram (block row q is formed
+    against columns start_q .. ns - 1 only): 128 wide up to ns = 1024, else three blocks
+    cut near 0.43 ns and 0.75 ns."""
+    if ns < 256:
+        return [0, ns]
+    if ns <= 1024:
+        return list(range(0, ns, 128)) + [ns]
+    return [0, int(0.43 * ns / 128 + 0.5) * 128, int(0.75 * ns / 128 + 0.5) * 128, ns]
+
+
 def gemm_figures(nd: int, ns: int, prec: int, gram_ms: float, rot_ms: float, fp64: bool):
     """Algorithmic and executed MFMA flops of one step's projection (two Gram products) and rotation."""
     alg = 2.0 * nd * ns * (ns + 1) * 2 + 2.0 * nd * ns * ns
     nt = (ns + 127) // 128
     if fp64:
-        gram_exec = 2 * (2.0 * nd * ns * ns)                          # rocBLAS dgemm: full Ns x Ns products
+        b = gram_block_starts(ns)                                     # rocBLAS dgemm per column block
+        gram_exec = 2 * sum(2.0 * nd * (b[q + 1] - b[q]) * (ns - b[q]) for q in range(len(b) - 1))
         rot_exec = 2.0 * nd * ns * ns
         mult, peak, unit_dtype = 1, FP64_MFMA_PEAK_TFS, "f64"
     else:

@@ -149,12 +149,39 @@ namespace {
 // strided-batched dgemm, the tail rows (fewer than splits) as one more dgemm, and the
 // partial products summed in a fixed order.  Chunks are no shorter than 2048 rows and
 // about 4096 output tiles of 128 x 128 are in flight over all chunks.
+// Only the upper triangle of the symmetric product is needed: the columns are cut into
+// blocks and block row i is formed against columns [start_i, ns) alone, which skips most
+// of the lower triangle's work.
+constexpr int kMaxGramBlocks = 8;
+
 struct BlasGram {
   int splits = 1;
   int64_t kc = 0, tail = 0;
   int nparts = 1;
   size_t bytes = 0;
+  int nblk = 1;                         // column blocks
+  int start[kMaxGramBlocks + 1] = {0};  // block b is columns [start[b], start[b+1])
 };
+
+// Column blocks of the upper-triangle Gram (split-K batches of rocBLAS dgemm, measured at
+// ns = 600 and 1200): up to ns = 1024, blocks of 128 columns (ns = 600: 2.6 vs 4.2 ms for
+// the full product); above, three blocks cut near 0.43 ns and 0.75 ns (ns = 1200 at 512
+// and 896: 21.0 vs 28.8 ms); small blocks run too few tiles to pay.
+void gram_blocks(int ns, int& nblk, int* start) {
+  nblk = 0;
+  start[0] = 0;
+  if (ns < 256) {
+    nblk = 1;
+  } else if (ns <= 128 * kMaxGramBlocks) {
+    for (int c = 128; c < ns; c += 128) start[++nblk] = c;
+    ++nblk;
+  } else {
+    start[1] = (int)std::lround(0.43 * ns / 128.0) * 128;
+    start[2] = (int)std::lround(0.75 * ns / 128.0) * 128;
+    nblk = 3;
+  }
+  start[nblk] = ns;
+}
 
 BlasGram plan_blas_gram(int64_t nd, int ns) {
   BlasGram b;
@@ -164,6 +191,7 @@ BlasGram plan_blas_gram(int64_t nd, int ns) {
   b.tail = nd - b.kc * b.splits;
   b.nparts = b.splits + (b.tail > 0 ? 1 : 0);
   b.bytes = (size_t)b.nparts * ns * ns * sizeof(double);
+  gram_blocks(ns, b.nblk, b.start);
   return b;
 }
 
@@ -551,14 +579,21 @@ void blas_gram(chefsi_handle* h, const double* X, const double* Y, int ns, const
     ProfScope ps(h, P_GRAM, s);
     BLAS_TRY(rocblas_set_stream(h->blas, s));
     BLAS_TRY(rocblas_set_workspace(h->blas, at<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
-    BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                                           (rocblas_int)b.kc, &one, X, ld, b.kc, Y, ld, b.kc, &zero, part, ns,
-                                           (rocblas_stride)ns * ns, b.splits));
-    if (b.tail > 0) {
-      const int64_t k0 = b.kc * b.splits;
-      BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                             (rocblas_int)b.tail, &one, X + k0, ld, Y + k0, ld, &zero,
-                             part + (size_t)b.splits * ns * ns, ns));
+    for (int q = 0; q < b.nblk; ++q) {
+      // block row q against columns [r0, ns): rows r0 .. r0 + m - 1 of every partial
+      const int r0 = b.start[q], m = b.start[q + 1] - r0, n = ns - r0;
+      const double* Xq = X + (size_t)r0 * h->nd;
+      const double* Yq = Y + (size_t)r0 * h->nd;
+      double* Pq = part + r0 + (size_t)r0 * ns;
+      BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                                             (rocblas_int)b.kc, &one, Xq, ld, b.kc, Yq, ld, b.kc, &zero, Pq, ns,
+                                             (rocblas_stride)ns * ns, b.splits));
+      if (b.tail > 0) {
+        const int64_t k0 = b.kc * b.splits;
+        BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                               (rocblas_int)b.tail, &one, Xq + k0, ld, Yq + k0, ld, &zero,
+                               Pq + (size_t)b.splits * ns * ns, ns));
+      }
     }
     ps.done();
   }
@@ -591,21 +626,29 @@ void panel_gram(chefsi_handle* h, const float* X, const double* Y, int ns, const
       const double* beta = r0 == 0 ? &zero : &one;
       HIP_TRY(launch_widen_rows(X + r0, h->nd, r, ns, W, p.rows, s));
       const int64_t nfull = r / p.kc, tail = r - nfull * p.kc;
-      if (nfull > 0) {
-        BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                                               (rocblas_int)p.kc, &one, W, ldw, p.kc, Y + r0, ldy, p.kc, beta, partH,
-                                               ns, pst, (rocblas_int)nfull));
-        BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                                               (rocblas_int)p.kc, &one, W, ldw, p.kc, W, ldw, p.kc, beta, partM, ns,
-                                               pst, (rocblas_int)nfull));
-      }
-      if (tail > 0) {  // only in a last, partial panel: nfull < splits and r0 > 0
-        const int64_t k0 = nfull * p.kc;
-        BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                               (rocblas_int)tail, &one, W + k0, ldw, Y + r0 + k0, ldy, &one, partH + nfull * pst,
-                               ns));
-        BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, ns, ns,
-                               (rocblas_int)tail, &one, W + k0, ldw, W + k0, ldw, &one, partM + nfull * pst, ns));
+      for (int q = 0; q < L.bgram.nblk; ++q) {
+        // upper triangle only: block row q of the product against columns [c0, ns)
+        const int c0 = L.bgram.start[q], m = L.bgram.start[q + 1] - c0, n = ns - c0;
+        const double* Wq = W + (size_t)c0 * p.rows;
+        const double* Yq = Y + r0 + (size_t)c0 * h->nd;
+        const size_t co = c0 + (size_t)c0 * ns;
+        if (nfull > 0) {
+          BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                                                 (rocblas_int)p.kc, &one, Wq, ldw, p.kc, Yq, ldy, p.kc, beta,
+                                                 partH + co, ns, pst, (rocblas_int)nfull));
+          BLAS_TRY(rocblas_dgemm_strided_batched(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                                                 (rocblas_int)p.kc, &one, Wq, ldw, p.kc, Wq, ldw, p.kc, beta,
+                                                 partM + co, ns, pst, (rocblas_int)nfull));
+        }
+        if (tail > 0) {  // only in a last, partial panel: nfull < splits and r0 > 0
+          const int64_t k0 = nfull * p.kc;
+          BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                                 (rocblas_int)tail, &one, Wq + k0, ldw, Yq + k0, ldy, &one,
+                                 partH + co + nfull * pst, ns));
+          BLAS_TRY(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, n,
+                                 (rocblas_int)tail, &one, Wq + k0, ldw, Wq + k0, ldw, &one,
+                                 partM + co + nfull * pst, ns));
+        }
       }
     }
     ps.done();
