@@ -234,6 +234,23 @@ def kb_projectors(n, h, bc, atoms, nproj_per_atom, rc=PROJ_RC, sigma=PROJ_SIGMA,
             np.full(n_atoms * nproj_per_atom, gamma, dtype=np.float64))
 
 
+def support_images(prob: Problem) -> np.ndarray:
+    """(sum n_J, 3) int32: for every support point of atom J, the lattice image m (per
+    periodic direction; 0 in Dirichlet ones) with point = R_J + m L + offset, offset the
+    minimum-image displacement used to build chi_J."""
+    nx, ny, nz = prob.n
+    L = _box(prob.n, prob.h)
+    out = np.zeros((len(prob.supp_idx), 3), dtype=np.int32)
+    for J in range(prob.n_atoms):
+        lo, hi = int(prob.supp_ptr[J]), int(prob.supp_ptr[J + 1])
+        lin = np.asarray(prob.supp_idx[lo:hi], dtype=np.int64)
+        coords = (lin % nx, (lin // nx) % ny, lin // (nx * ny))
+        for d in range(3):
+            if prob.bc[d] == PERIODIC:
+                out[lo:hi, d] = np.round((coords[d] * prob.h[d] - prob.atoms[J][d]) / L[d]).astype(np.int32)
+    return out
+
+
 def make_problem(cfg: Config) -> Problem:
     atoms = atom_positions(cfg)
     veff = gaussian_wells(cfg.n, cfg.h, cfg.bc, atoms)
