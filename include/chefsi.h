@@ -282,6 +282,50 @@ const char* chefsi_last_error(const chefsi_handle_t* h);
 /* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
 int chefsi_version(void);
 
+/* ---- CheFSI at a Bloch wavevector (complex FP64) ----------------------------
+ * Sec. 2 of the paper: Gamma-point and isolated systems run in real arithmetic,
+ * every other Brillouin-zone sample in complex double precision; H of Alg. 1 is
+ * the Hamiltonian of one Bloch wavevector k (bohr^-1).  Orbitals are Bloch
+ * periodic, psi(r + L_d e_d) = exp(i k_d L_d) psi(r), L_d = n_d h_d, in every
+ * periodic direction (k_d is ignored in Dirichlet ones):
+ *   - the FD ghosts of Sec. 2.1 across a periodic face carry exp(+-i k_d L_d);
+ *   - every projector is its Bloch sum: the value of support point s of atom J
+ *     becomes chi_J(s) exp(i k.(m_s L)), where m_s (supp_img[3 s .. 3 s + 2],
+ *     HOST int32, one triple per support point in supp_idx order) is the lattice
+ *     image the point belongs to: point = R_J + m_s L + the displacement chi_J
+ *     was evaluated at (the truncation radius must be below half the cell so a
+ *     point sees one image);
+ *   - V_nl psi = sum_J chi~_J Gamma_J (chi~_J^H psi[S_J]) dV.
+ * Blocks are DEVICE, complex FP64 with interleaved real and imaginary parts
+ * (re, im), Nd x ns column major (ld = Nd): a torch.complex128 tensor of shape
+ * (ns, Nd).  A step is Alg. 1 with conjugate transposes: Hs = X~^H H X~,
+ * Ms = X~^H X~, Hs Z = Ms Z D (Hermitian definite, ascending D), X = X~ Z.
+ * The handle holds its own copies of all host inputs (freed by
+ * chefsi_kpoint_destroy); calls are ordered on their stream; max_ns <= 65535.
+ * Errors as for the real handle (INVALID_ARG, WORKSPACE, NOT_POSDEF, EIG,
+ * NONFINITE, SOLVER, HIP, OOM); after an error the handle stays usable and X
+ * is unspecified. */
+typedef struct chefsi_kpoint chefsi_kpoint_t;
+
+int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
+                         const int32_t* supp_img, const double* kvec, int32_t max_ns, chefsi_kpoint_t** out);
+void chefsi_kpoint_destroy(chefsi_kpoint_t* h);
+const char* chefsi_kpoint_last_error(const chefsi_kpoint_t* h);
+
+/* Exact device workspace (bytes, 256-byte aligned base required) of the calls below. */
+int chefsi_kpoint_workspace_bytes(chefsi_kpoint_t* h, int32_t ns, size_t* bytes);
+
+/* Y = H_k X (X and Y distinct device blocks of ns orbitals). */
+int chefsi_kpoint_apply_h(chefsi_kpoint_t* h, const void* X, void* Y, int32_t ns, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* One complex CheFSI step (Alg. 1): the scaled Chebyshev filter of degree >= 1
+ * with bounds lam_lo <= lam_cut < lam_hi, projection, Hermitian-definite
+ * eigensolve, rotation.  X is updated in place; ritz_host (HOST, ns doubles)
+ * receives D ascending. */
+int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
+                       double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host);
+
 #ifdef __cplusplus
 }
 #endif

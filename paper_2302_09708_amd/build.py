@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libchefsi.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["hx_apply.hip", "nonlocal.hip", "gemm.hip", "gemm_bf16.hip", "lanczos.hip", "forces.hip", "api.cpp"]
+SOURCES = ["hx_apply.hip", "nonlocal.hip", "gemm.hip", "gemm_bf16.hip", "lanczos.hip", "forces.hip", "kpoint.hip", "api.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -41,7 +41,8 @@ EXPORTS = (
     "chefsi_profile_reset", "chefsi_profile_read", "chefsi_last_info", "chefsi_strerror",
     "chefsi_last_error", "chefsi_version", "chefsi_lanczos_workspace_bytes", "chefsi_lanczos_bound",
     "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
-    "chefsi_kinetic_stress",
+    "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
+    "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
 )
 
 
@@ -109,6 +110,15 @@ def load(path: str = LIB_PATH):
     lib.chefsi_last_error.argtypes = [vp]
     lib.chefsi_last_error.restype = C.c_char_p
     lib.chefsi_version.argtypes = []
+    lib.chefsi_kpoint_create.argtypes = [C.POINTER(Grid), pd, C.POINTER(Nonlocal), C.POINTER(C.c_int32), pd, i32,
+                                         C.POINTER(vp)]
+    lib.chefsi_kpoint_destroy.argtypes = [vp]
+    lib.chefsi_kpoint_destroy.restype = None
+    lib.chefsi_kpoint_last_error.argtypes = [vp]
+    lib.chefsi_kpoint_last_error.restype = C.c_char_p
+    lib.chefsi_kpoint_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    lib.chefsi_kpoint_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_kpoint_step.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd]
     _lib = lib
     return lib
 
@@ -129,6 +139,93 @@ def _stream(stream) -> int:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def _marshal(problem):
+    """(Grid, Nonlocal, veff array, arrays to keep alive) for a problem."""
+    g = Grid()
+    for d in range(3):
+        g.n[d] = int(problem.n[d])
+        g.h[d] = float(problem.h[d])
+        g.bc[d] = int(problem.bc[d])
+    g.fd_order = int(problem.fd_order)
+    veff = np.ascontiguousarray(problem.veff, dtype=np.float64)
+    keep = [veff]
+    nl = Nonlocal()
+    nl.n_atoms = int(len(problem.nproj))
+    if nl.n_atoms > 0:
+        arrs = [np.ascontiguousarray(problem.supp_ptr, dtype=np.int64),
+                np.ascontiguousarray(problem.supp_idx, dtype=np.int32),
+                np.ascontiguousarray(problem.nproj, dtype=np.int32),
+                np.ascontiguousarray(problem.chi, dtype=np.float64),
+                np.ascontiguousarray(problem.gamma, dtype=np.float64)]
+        keep += arrs
+        nl.supp_ptr = arrs[0].ctypes.data_as(C.POINTER(C.c_int64))
+        nl.supp_idx = arrs[1].ctypes.data_as(C.POINTER(C.c_int32))
+        nl.nproj = arrs[2].ctypes.data_as(C.POINTER(C.c_int32))
+        nl.chi = arrs[3].ctypes.data_as(C.POINTER(C.c_double))
+        nl.gamma = arrs[4].ctypes.data_as(C.POINTER(C.c_double))
+    return g, nl, veff, keep
+
+
+class KPoint:
+    """One Hamiltonian at a Bloch wavevector k (chefsi_kpoint_create / _destroy); blocks
+    are torch.complex128 tensors of shape (ns, Nd).  supp_img: (sum n_J, 3) int32 image
+    of every support point."""
+
+    def __init__(self, problem, k, supp_img, max_ns: int = 1):
+        lib = load()
+        self._lib = lib
+        g, nl, veff, keep = _marshal(problem)
+        img = np.ascontiguousarray(supp_img, dtype=np.int32).reshape(-1)
+        kv = np.ascontiguousarray(k, dtype=np.float64).reshape(3)
+        h = C.c_void_p()
+        st = lib.chefsi_kpoint_create(C.byref(g), veff.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nl),
+                                      img.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      kv.ctypes.data_as(C.POINTER(C.c_double)), int(max_ns), C.byref(h))
+        del keep
+        if st != OK:
+            raise ChefsiError(st, lib.chefsi_strerror(st).decode())
+        self.h = h
+        self.nd = int(np.prod(problem.n))
+        self.max_ns = int(max_ns)
+
+    def _check(self, st: int):
+        if st != OK:
+            msg = self._lib.chefsi_kpoint_last_error(self.h).decode() or self._lib.chefsi_strerror(st).decode()
+            raise ChefsiError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.chefsi_kpoint_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, ns: int) -> int:
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_kpoint_workspace_bytes(self.h, int(ns), C.byref(b)))
+        return int(b.value)
+
+    def workspace(self, ns: int):
+        import torch
+        return torch.empty(self.workspace_bytes(ns), dtype=torch.uint8, device="cuda")
+
+    def apply_h(self, X, Y, ns, ws, stream=None):
+        self._check(self._lib.chefsi_kpoint_apply_h(self.h, _ptr(X), _ptr(Y), int(ns), _ptr(ws),
+                                                     ws.numel() * ws.element_size(), _stream(stream)))
+
+    def step(self, X, ns, degree, lam_lo, lam_cut, lam_hi, ws, stream=None) -> np.ndarray:
+        d = np.zeros(int(ns), dtype=np.float64)
+        self._check(self._lib.chefsi_kpoint_step(self.h, _ptr(X), int(ns), int(degree), float(lam_lo),
+                                                  float(lam_cut), float(lam_hi), _ptr(ws),
+                                                  ws.numel() * ws.element_size(), _stream(stream),
+                                                  d.ctypes.data_as(C.POINTER(C.c_double))))
+        return d
 
 
 class Handle:

@@ -1823,3 +1823,483 @@ int chefsi_profile_read(chefsi_handle_t* h, int32_t kernel_id, double* total_ms,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// CheFSI at a Bloch wavevector (complex FP64; Sec. 2: every Brillouin-zone sample other
+// than Gamma runs in complex double precision).  H_k = T_k + Veff + V_nl,k with
+// Bloch-phased FD ghosts and Bloch-summed projectors; the step is Alg. 1 with conjugate
+// transposes: Hs = X~^H H X~, Ms = X~^H X~ (rocBLAS zgemm), Ms = U^H U, C = U^-H Hs U^-1,
+// C = W D W^H (rocSOLVER zheevd), Z = U^-1 W, X = X~ Z.
+// ---------------------------------------------------------------------------
+struct chefsi_kpoint {
+  int device = 0;
+  int n[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0};
+  int radius = 6;
+  int64_t nd = 0;
+  int max_ns = 0;
+  double kvec[3] = {0, 0, 0};
+  std::vector<double> w;
+  int n_atoms = 0, np_tot = 0, n_pts = 0;
+  double* veff = nullptr;
+  int *supp_off = nullptr, *supp_idx = nullptr, *nproj = nullptr, *poff = nullptr;
+  int64_t* chi_off = nullptr;
+  double2* chi = nullptr;
+  double* gdv = nullptr;
+  int *pt = nullptr, *ptr = nullptr, *col = nullptr;
+  double2* val = nullptr;
+  double* pinned = nullptr;
+  rocblas_handle blas = nullptr;
+  std::map<int, size_t> solver_ws_cache;
+  std::string last_error;
+};
+
+namespace {
+
+struct ZLayout {
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, solver = 0, total = 0, solver_bytes = 0;
+};
+
+size_t zsolver_workspace(chefsi_kpoint* h, int ns) {
+  auto it = h->solver_ws_cache.find(ns);
+  if (it != h->solver_ws_cache.end()) return it->second;
+  const rocblas_double_complex one(1.0, 0.0);
+  size_t best = 0, sz = 0;
+  auto query = [&](auto&& call) {
+    BLAS_TRY(rocblas_start_device_memory_size_query(h->blas));
+    call();
+    BLAS_TRY(rocblas_stop_device_memory_size_query(h->blas, &sz));
+    best = std::max(best, sz);
+  };
+  const rocblas_int ld = (rocblas_int)h->nd;
+  query([&] { rocsolver_zpotrf(h->blas, rocblas_fill_upper, ns, nullptr, ns, nullptr); });
+  query([&] {
+    rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                  rocblas_diagonal_non_unit, ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocblas_ztrsm(h->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                  ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none, rocblas_diagonal_non_unit,
+                  ns, ns, &one, nullptr, ns, nullptr, ns);
+  });
+  query([&] {
+    rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr, nullptr);
+  });
+  query([&] {
+    rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one, nullptr,
+                  ld, nullptr, ld, &one, nullptr, ns);
+  });
+  query([&] {
+    rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, ld, ns, ns, &one, nullptr, ld, nullptr, ns,
+                  &one, nullptr, ld);
+  });
+  h->solver_ws_cache[ns] = best;
+  return best;
+}
+
+ZLayout zlayout(chefsi_kpoint* h, int ns) {
+  ZLayout L;
+  size_t off = 0;
+  L.bufB = off;
+  off += align256((size_t)h->nd * ns * 16);
+  L.alpha = off;
+  off += align256((size_t)std::max(1, h->np_tot) * ns * 16);
+  L.hs = off;
+  off += align256((size_t)ns * ns * 16);
+  L.ms = off;
+  off += align256((size_t)ns * ns * 16);
+  L.d = off;
+  off += align256((size_t)ns * 8);
+  L.e = off;
+  off += align256((size_t)ns * 8);
+  L.info = off;
+  off += 256;
+  L.solver = off;
+  L.solver_bytes = zsolver_workspace(h, ns);
+  off += align256(std::max<size_t>(L.solver_bytes, 256));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* zat(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+template <typename T>
+T* kupload(const T* src, size_t n) {
+  T* d = nullptr;
+  if (n == 0) return nullptr;
+  if (hipMalloc(&d, n * sizeof(T)) != hipSuccess) throw Error{CHEFSI_ERR_OOM, "device allocation failed"};
+  hipError_t e = hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    throw Error{CHEFSI_ERR_HIP, std::string("upload: ") + hipGetErrorString(e)};
+  }
+  return d;
+}
+
+void krelease(chefsi_kpoint* h) {
+  void* ptrs[] = {h->veff, h->supp_off, h->supp_idx, h->nproj, h->poff, h->chi_off, h->chi, h->gdv,
+                  h->pt,   h->ptr,      h->col,      h->val};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->blas) rocblas_destroy_handle(h->blas);
+}
+
+// out = sa ((H_k x) - sc x) + sb prev: projector gather, stencil + Veff + recurrence, scatter.
+void zapply(chefsi_kpoint* h, const double2* x, const double2* prev, double2* out, int ns, double sa, double sc,
+            double sb, double2* alpha, hipStream_t s) {
+  if (h->np_tot > 0) {
+    ZNlArgs g{};
+    g.x = x;
+    g.nd = h->nd;
+    g.n_atoms = h->n_atoms;
+    g.supp_off = h->supp_off;
+    g.supp_idx = h->supp_idx;
+    g.chi_off = h->chi_off;
+    g.nproj = h->nproj;
+    g.poff = h->poff;
+    g.chi = h->chi;
+    g.gdv = h->gdv;
+    g.alpha = alpha;
+    g.np_tot = h->np_tot;
+    HIP_TRY(launch_zproject(g, ns, s));
+  }
+  ZHxArgs a{};
+  a.x = x;
+  a.prev = prev;
+  a.out = out;
+  a.veff = h->veff;
+  a.r = h->radius;
+  a.nd = h->nd;
+  double sumh = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = h->n[d];
+    a.per[d] = h->bc[d] == 0;
+    sumh += 1.0 / (h->h[d] * h->h[d]);
+    const double th = h->bc[d] == 0 ? h->kvec[d] * h->n[d] * h->h[d] : 0.0;
+    a.ph[d] = make_double2(std::cos(th), std::sin(th));
+    for (int p = 0; p <= kMaxRadius; ++p) a.cw[d][p] = p <= h->radius ? -0.5 * h->w[p] / (h->h[d] * h->h[d]) : 0.0;
+  }
+  a.c0 = -0.5 * h->w[0] * sumh;
+  a.sa = sa;
+  a.sc = sc;
+  a.sb = sb;
+  HIP_TRY(launch_zhx(a, ns, s));
+  if (h->n_pts > 0) {
+    ZNsArgs n{};
+    n.out = out;
+    n.nd = h->nd;
+    n.n_pts = h->n_pts;
+    n.pt = h->pt;
+    n.ptr = h->ptr;
+    n.col = h->col;
+    n.val = h->val;
+    n.alpha = alpha;
+    n.np_tot = h->np_tot;
+    n.sa = sa;
+    HIP_TRY(launch_zscatter(n, ns, s));
+  }
+}
+
+template <typename F>
+int kguarded(chefsi_kpoint* h, F&& f) {
+  if (h == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  try {
+    h->last_error.clear();
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) HIP_TRY(hipSetDevice(h->device));
+    f();
+    return CHEFSI_OK;
+  } catch (const Error& e) {
+    h->last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    h->last_error = "host allocation failed";
+    return CHEFSI_ERR_OOM;
+  } catch (...) {
+    h->last_error = "unexpected exception";
+    return CHEFSI_ERR_HIP;
+  }
+}
+
+void kcheck_call(chefsi_kpoint* h, int ns, void* ws, size_t ws_bytes, ZLayout& L) {
+  check(ns >= 1 && ns <= h->max_ns, "ns must satisfy 1 <= ns <= max_ns");
+  check((int64_t)ns <= h->nd, "ns must not exceed Nd");
+  L = zlayout(h, ns);
+  if (ws == nullptr || ws_bytes < L.total)
+    throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_kpoint_workspace_bytes(ns)"};
+  check(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
+}
+
+}  // namespace
+
+extern "C" {
+
+int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
+                         const int32_t* supp_img, const double* kvec, int32_t max_ns, chefsi_kpoint_t** out) {
+  if (out == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (grid == nullptr || veff_host == nullptr || kvec == nullptr) return CHEFSI_ERR_INVALID_ARG;
+  chefsi_kpoint* h = nullptr;
+  try {
+    h = new chefsi_kpoint();
+  } catch (...) {
+    return CHEFSI_ERR_OOM;
+  }
+  try {
+    check(grid->fd_order >= 2 && grid->fd_order <= 12 && grid->fd_order % 2 == 0, "fd_order must be even, 2..12");
+    h->radius = grid->fd_order / 2;
+    int64_t nd = 1;
+    for (int d = 0; d < 3; ++d) {
+      check(grid->n[d] >= 1, "grid sizes must be >= 1");
+      check(grid->bc[d] == 0 || grid->bc[d] == 1, "bc must be 0 (periodic) or 1 (Dirichlet)");
+      check(std::isfinite(grid->h[d]) && grid->h[d] > 0.0, "grid spacing must be positive");
+      check(std::isfinite(kvec[d]), "k must be finite");
+      if (grid->bc[d] == 0) check(grid->n[d] >= h->radius, "periodic direction needs n >= fd_order/2");
+      h->n[d] = grid->n[d];
+      h->h[d] = grid->h[d];
+      h->bc[d] = grid->bc[d];
+      h->kvec[d] = kvec[d];
+      nd *= grid->n[d];
+    }
+    check(nd < (int64_t)1 << 31, "Nd must be below 2^31");
+    check(max_ns >= 1 && (int64_t)max_ns <= nd && max_ns <= 65535, "max_ns must satisfy 1 <= max_ns <= min(Nd, 65535)");
+    h->nd = nd;
+    h->max_ns = max_ns;
+    h->w = fd_weights(grid->fd_order);
+    const double dv = grid->h[0] * grid->h[1] * grid->h[2];
+    std::vector<double> veff(veff_host, veff_host + nd);
+    for (double v : veff) check(std::isfinite(v), "Veff must be finite");
+
+    std::vector<int> soff, sidx, nproj, poff, pts, ptr, cols;
+    std::vector<int64_t> coff;
+    std::vector<double2> chi, vals;
+    std::vector<double> gdv;
+    if (nl != nullptr && nl->n_atoms > 0) {
+      check(nl->supp_ptr && nl->supp_idx && nl->nproj && nl->chi && nl->gamma && supp_img, "null projector array");
+      const int na = nl->n_atoms;
+      const int64_t nsupp = nl->supp_ptr[na];
+      check(nl->supp_ptr[0] == 0 && nsupp >= 0 && nsupp < (int64_t)1 << 31, "bad supp_ptr");
+      double kl[3];
+      for (int d = 0; d < 3; ++d) kl[d] = grid->bc[d] == 0 ? kvec[d] * grid->n[d] * grid->h[d] : 0.0;
+      soff.resize(na + 1);
+      coff.resize(na);
+      poff.resize(na);
+      nproj.assign(nl->nproj, nl->nproj + na);
+      int64_t c = 0;
+      int p = 0;
+      for (int J = 0; J < na; ++J) {
+        check(nl->supp_ptr[J + 1] >= nl->supp_ptr[J], "supp_ptr must be non-decreasing");
+        check(nproj[J] >= 1, "nproj must be >= 1");
+        soff[J] = (int)nl->supp_ptr[J];
+        coff[J] = c;
+        poff[J] = p;
+        const int64_t nj = nl->supp_ptr[J + 1] - nl->supp_ptr[J];
+        for (int64_t s = 0; s < nj; ++s) {
+          const int64_t i = nl->supp_idx[nl->supp_ptr[J] + s];
+          check(i >= 0 && i < nd, "support index outside the grid");
+          if (s > 0) check(i > nl->supp_idx[nl->supp_ptr[J] + s - 1], "support indices must increase");
+        }
+        c += nj * nproj[J];
+        p += nproj[J];
+      }
+      check(p < (1 << 30) && c < ((int64_t)1 << 31), "too many projectors");
+      soff[na] = (int)nsupp;
+      h->n_atoms = na;
+      h->np_tot = p;
+      sidx.assign(nl->supp_idx, nl->supp_idx + nsupp);
+      // Bloch-phased projector values: chi~ = chi * exp(i k.(m L)), m the image of the point
+      chi.resize(c);
+      for (int J = 0; J < na; ++J) {
+        const int64_t nj = nl->supp_ptr[J + 1] - nl->supp_ptr[J];
+        for (int64_t s = 0; s < nj; ++s) {
+          const int64_t g = nl->supp_ptr[J] + s;
+          double th = 0.0;
+          for (int d = 0; d < 3; ++d) th += kl[d] * supp_img[3 * g + d];
+          const double cr = std::cos(th), ci = std::sin(th);
+          for (int a = 0; a < nproj[J]; ++a) {
+            const double v = nl->chi[coff[J] + a * nj + s];
+            check(std::isfinite(v), "chi must be finite");
+            chi[coff[J] + a * nj + s] = make_double2(v * cr, v * ci);
+          }
+        }
+      }
+      gdv.resize(p);
+      for (int q = 0; q < p; ++q) {
+        check(std::isfinite(nl->gamma[q]), "gamma must be finite");
+        gdv[q] = nl->gamma[q] * dv;
+      }
+      // point-major entries for the scatter: grid points in increasing order, atoms in order
+      std::vector<int> cnt(nd + 1, 0);
+      for (int J = 0; J < na; ++J)
+        for (int64_t s = nl->supp_ptr[J]; s < nl->supp_ptr[J + 1]; ++s) cnt[sidx[s] + 1] += nproj[J];
+      for (int64_t i = 0; i < nd; ++i) cnt[i + 1] += cnt[i];
+      const int64_t nent = cnt[nd];
+      std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+      cols.resize(nent);
+      vals.resize(nent);
+      for (int J = 0; J < na; ++J) {
+        const int64_t nj = nl->supp_ptr[J + 1] - nl->supp_ptr[J];
+        for (int64_t s = 0; s < nj; ++s) {
+          const int i = sidx[nl->supp_ptr[J] + s];
+          for (int a = 0; a < nproj[J]; ++a) {
+            const int pos = fill[i]++;
+            cols[pos] = poff[J] + a;
+            vals[pos] = chi[coff[J] + a * nj + s];
+          }
+        }
+      }
+      ptr.push_back(0);
+      for (int64_t i = 0; i < nd; ++i)
+        if (cnt[i + 1] > cnt[i]) {
+          pts.push_back((int)i);
+          ptr.push_back(cnt[i + 1]);
+        }
+      h->n_pts = (int)pts.size();
+    }
+
+    HIP_TRY(hipGetDevice(&h->device));
+    BLAS_TRY(rocblas_create_handle(&h->blas));
+    BLAS_TRY(rocblas_set_atomics_mode(h->blas, rocblas_atomics_not_allowed));
+    if (hipHostMalloc((void**)&h->pinned, (size_t)max_ns * sizeof(double) + 64, hipHostMallocDefault) != hipSuccess) {
+      h->pinned = nullptr;
+      throw Error{CHEFSI_ERR_OOM, "pinned host allocation failed"};
+    }
+    h->veff = kupload(veff.data(), veff.size());
+    if (h->np_tot > 0) {
+      h->supp_off = kupload(soff.data(), soff.size());
+      h->supp_idx = kupload(sidx.data(), sidx.size());
+      h->nproj = kupload(nproj.data(), nproj.size());
+      h->poff = kupload(poff.data(), poff.size());
+      h->chi_off = kupload(coff.data(), coff.size());
+      h->chi = kupload(chi.data(), chi.size());
+      h->gdv = kupload(gdv.data(), gdv.size());
+      h->pt = kupload(pts.data(), pts.size());
+      h->ptr = kupload(ptr.data(), ptr.size());
+      h->col = kupload(cols.data(), cols.size());
+      h->val = kupload(vals.data(), vals.size());
+    }
+    *out = h;
+    return CHEFSI_OK;
+  } catch (const Error& e) {
+    krelease(h);
+    delete h;
+    return e.status;
+  } catch (...) {
+    krelease(h);
+    delete h;
+    return CHEFSI_ERR_OOM;
+  }
+}
+
+void chefsi_kpoint_destroy(chefsi_kpoint_t* h) {
+  if (h == nullptr) return;
+  (void)hipSetDevice(h->device);
+  krelease(h);
+  delete h;
+}
+
+const char* chefsi_kpoint_last_error(const chefsi_kpoint_t* h) { return h ? h->last_error.c_str() : ""; }
+
+int chefsi_kpoint_workspace_bytes(chefsi_kpoint_t* h, int32_t ns, size_t* bytes) {
+  return kguarded(h, [&] {
+    check(bytes != nullptr, "null pointer");
+    check(ns >= 1 && ns <= h->max_ns, "ns must satisfy 1 <= ns <= max_ns");
+    *bytes = zlayout(h, ns).total;
+  });
+}
+
+int chefsi_kpoint_apply_h(chefsi_kpoint_t* h, const void* X, void* Y, int32_t ns, void* ws, size_t ws_bytes,
+                          void* stream) {
+  return kguarded(h, [&] {
+    check(X != nullptr && Y != nullptr, "null pointer");
+    check(X != Y, "X and Y must not alias");
+    ZLayout L;
+    kcheck_call(h, ns, ws, ws_bytes, L);
+    zapply(h, (const double2*)X, nullptr, (double2*)Y, ns, 1.0, 0.0, 0.0, zat<double2>(ws, L.alpha),
+           (hipStream_t)stream);
+  });
+}
+
+int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
+                       double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host) {
+  return kguarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check(degree >= 1, "degree must be >= 1");
+    check_bounds(lam_lo, lam_cut, lam_hi);
+    ZLayout L;
+    kcheck_call(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    double2* A = (double2*)X;
+    double2* B = zat<double2>(ws, L.bufB);
+    double2* alpha = zat<double2>(ws, L.alpha);
+    double2* Hs = zat<double2>(ws, L.hs);
+    double2* Ms = zat<double2>(ws, L.ms);
+    double* D = zat<double>(ws, L.d);
+    rocblas_int* info = zat<rocblas_int>(ws, L.info);
+    // scaled Chebyshev filter (Alg. 1, Filtering), the same scalars as the real path
+    const double c = 0.5 * (lam_hi + lam_cut);
+    const double e = 0.5 * (lam_hi - lam_cut);
+    const double s1 = e / (lam_lo - c);
+    double sig = s1;
+    zapply(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s);
+    double2* cur = B;
+    double2* other = A;
+    for (int k = 1; k < degree; ++k) {
+      const double sig_next = 1.0 / (2.0 / s1 - sig);
+      zapply(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s);
+      std::swap(cur, other);
+      sig = sig_next;
+    }
+    double2* Xf = cur;
+    double2* Yf = other;
+    zapply(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
+    // projection (upper triangles made Hermitian)
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    const rocblas_int ld = (rocblas_int)h->nd;
+    BLAS_TRY(rocblas_set_stream(h->blas, s));
+    BLAS_TRY(rocblas_set_workspace(h->blas, zat<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
+    auto zc = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
+    auto zm = [](double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
+    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one,
+                           zc(Xf), ld, zc(Yf), ld, &zero, zm(Hs), ns));
+    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one,
+                           zc(Xf), ld, zc(Xf), ld, &zero, zm(Ms), ns));
+    HIP_TRY(launch_zherm_upper(Hs, ns, s));
+    HIP_TRY(launch_zherm_upper(Ms, ns, s));
+    // Hermitian-definite eigenproblem (Alg. 1, Diagonalization)
+    BLAS_TRY(rocsolver_zpotrf(h->blas, rocblas_fill_upper, ns, zm(Ms), ns, info));
+    BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                           rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
+    BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
+    BLAS_TRY(rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, zm(Hs), ns, D,
+                              zat<double>(ws, L.e), info + 1));
+    BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                           rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
+    // rotation (Alg. 1, Rotation): X = X~ Z into the buffer Y~ held
+    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, ld, ns, ns, &one, zc(Xf), ld,
+                           zc(Hs), ns, &zero, zm(Yf), ld));
+    if (Yf != A) HIP_TRY(hipMemcpyAsync(A, Yf, (size_t)h->nd * ns * 16, hipMemcpyDeviceToDevice, s));
+    double* d = h->pinned;
+    rocblas_int* inf = reinterpret_cast<rocblas_int*>(h->pinned + h->max_ns);
+    HIP_TRY(hipMemcpyAsync(d, D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(inf, info, 2 * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (inf[0] > 0) throw Error{CHEFSI_ERR_NOT_POSDEF, "Cholesky of the overlap matrix failed"};
+    if (inf[1] > 0) throw Error{CHEFSI_ERR_EIG, "dense eigensolver did not converge"};
+    for (int i = 0; i < ns; ++i)
+      if (!std::isfinite(d[i])) throw Error{CHEFSI_ERR_NONFINITE, "non-finite Ritz value"};
+    if (ritz_host) std::memcpy(ritz_host, d, (size_t)ns * 8);
+  });
+}
+
+}  // extern "C"

@@ -254,4 +254,55 @@ hipError_t launch_lanczos_scale(const double* w, double inv, int64_t n, TV* out,
 template <typename TV>
 hipError_t launch_widen(const TV* x, int64_t n, double* w, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// H at a Bloch wavevector on complex FP64 blocks (interleaved re/im, Nd x Ns, ld Nd).
+// ---------------------------------------------------------------------------
+struct ZHxArgs {
+  const double2* x;
+  const double2* prev;  // may be null (sb unused)
+  double2* out;
+  const double* veff;
+  int n[3];
+  int per[3];       // 1 = periodic (Bloch-phased ghosts), 0 = Dirichlet (zero ghosts)
+  int r;
+  int64_t nd;
+  double c0;                     // -1/2 w0 sum_d h_d^-2
+  double cw[3][kMaxRadius + 1];  // -1/2 w_p / h_d^2
+  double2 ph[3];                 // exp(i k_d L_d)
+  double sa, sc, sb;
+};
+
+struct ZNlArgs {
+  const double2* x;
+  int64_t nd;
+  int n_atoms;
+  const int* supp_off;     // n_atoms + 1
+  const int* supp_idx;
+  const int64_t* chi_off;  // n_atoms, offset of chi~_J (n_J x np_J, column major)
+  const int* nproj;
+  const int* poff;
+  const double2* chi;      // Bloch-phased projector values
+  const double* gdv;       // gamma * dV per projector column
+  double2* alpha;          // ns x np_tot, projector column fastest
+  int np_tot;
+};
+
+struct ZNsArgs {
+  double2* out;
+  int64_t nd;
+  int n_pts;
+  const int* pt;      // n_pts grid points
+  const int* ptr;     // n_pts + 1 entry offsets
+  const int* col;     // projector column of every entry
+  const double2* val; // chi~ of every entry
+  const double2* alpha;
+  int np_tot;
+  double sa;
+};
+
+hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s);
+hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s);
+hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s);
+hipError_t launch_zherm_upper(double2* C, int ns, hipStream_t s);
+
 }  // namespace chefsi

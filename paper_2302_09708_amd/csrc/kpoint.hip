@@ -1,0 +1,166 @@
+// H at a Bloch wavevector k on complex FP64 orbitals (interleaved re/im, Nd x Ns column
+// major): Sec. 2 of the paper runs every Brillouin-zone sample other than Gamma in complex
+// double precision.  Three kernels, launched in this order on one stream:
+//   zproject  alpha[v, q] = gamma_q dV sum_{s in S_J} conj(chi~_J[s, a]) x[v, S_J[s]]
+//   zhx       out = sa ((T_k + Veff) x - sc x) + sb prev    (Bloch-phased FD ghosts)
+//   zscatter  out[v, p] += sa sum_{e in entries of p} chi~[e] alpha[v, col[e]]
+// chi~ carries the Bloch phase of the image each support point belongs to (set on the
+// host); the three-term filter recurrence uses the same real scalars as the real path.
+// Every sum runs in a fixed order: results are bitwise reproducible.
+#include "common.h"
+
+namespace chefsi {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// x~(i + p e_d) for one direction: the wrapped neighbour times the cell phase (periodic),
+// or zero outside a Dirichlet boundary.  Periodic directions have n >= r, so i + p wraps
+// at most once.
+__device__ __forceinline__ double2 neighbour(const double2* __restrict__ xv, int64_t i, int c, int p, int n,
+                                             int64_t stride, int periodic, double2 ph) {
+  int j = c + p;
+  if (j >= n) {
+    if (!periodic) return make_double2(0.0, 0.0);
+    return cmul(xv[i + (int64_t)(j - n - c) * stride], ph);
+  }
+  if (j < 0) {
+    if (!periodic) return make_double2(0.0, 0.0);
+    return cmul(xv[i + (int64_t)(j + n - c) * stride], make_double2(ph.x, -ph.y));
+  }
+  return xv[i + (int64_t)p * stride];
+}
+
+__global__ __launch_bounds__(256) void zhx_kernel(ZHxArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.nd) return;
+  const int64_t v = blockIdx.y;
+  const double2* __restrict__ xv = a.x + v * a.nd;
+  const int nx = a.n[0], ny = a.n[1];
+  const int c[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((int64_t)nx * ny))};
+  const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+  const double2 xi = xv[i];
+  const double diag = a.c0 + a.veff[i] - a.sc;
+  double re = diag * xi.x, im = diag * xi.y;
+  for (int d = 0; d < 3; ++d) {
+    for (int p = 1; p <= a.r; ++p) {
+      const double2 up = neighbour(xv, i, c[d], p, a.n[d], stride[d], a.per[d], a.ph[d]);
+      const double2 dn = neighbour(xv, i, c[d], -p, a.n[d], stride[d], a.per[d], a.ph[d]);
+      re += a.cw[d][p] * (up.x + dn.x);
+      im += a.cw[d][p] * (up.y + dn.y);
+    }
+  }
+  double2 o = make_double2(a.sa * re, a.sa * im);
+  if (a.prev != nullptr) {
+    const double2 pv = a.prev[v * a.nd + i];
+    o.x += a.sb * pv.x;
+    o.y += a.sb * pv.y;
+  }
+  a.out[v * a.nd + i] = o;
+}
+
+constexpr int kZThreads = 256;
+
+// one block per (atom, orbital); every thread sums its strided share of the support, then
+// a fixed-shape tree sums the threads
+__global__ __launch_bounds__(kZThreads) void zproject_kernel(ZNlArgs a) {
+  __shared__ double2 red[kZThreads];
+  const int J = blockIdx.x;
+  const int64_t v = blockIdx.y;
+  const int s0 = a.supp_off[J], nj = a.supp_off[J + 1] - s0;
+  const int npj = a.nproj[J];
+  const int64_t co = a.chi_off[J];
+  const double2* __restrict__ xv = a.x + v * a.nd;
+  for (int q = 0; q < npj; ++q) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = threadIdx.x; s < nj; s += kZThreads) {
+      const double2 t = cmulc(a.chi[co + (int64_t)q * nj + s], xv[a.supp_idx[s0 + s]]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kZThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        red[threadIdx.x].x += red[threadIdx.x + w].x;
+        red[threadIdx.x].y += red[threadIdx.x + w].y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int col = a.poff[J] + q;
+      const double g = a.gdv[col];
+      a.alpha[v * a.np_tot + col] = make_double2(g * red[0].x, g * red[0].y);
+    }
+    __syncthreads();
+  }
+}
+
+// one thread per (support point, orbital); every point is written by one thread
+__global__ __launch_bounds__(256) void zscatter_kernel(ZNsArgs a) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.n_pts) return;
+  const int64_t v = blockIdx.y;
+  const double2* __restrict__ al = a.alpha + v * a.np_tot;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int e = a.ptr[p]; e < a.ptr[p + 1]; ++e) {
+    const double2 t = cmul(a.val[e], al[a.col[e]]);
+    acc.x += t.x;
+    acc.y += t.y;
+  }
+  double2* o = a.out + v * a.nd + a.pt[p];
+  double2 cur = *o;
+  cur.x += a.sa * acc.x;
+  cur.y += a.sa * acc.y;
+  *o = cur;
+}
+
+// C <- Hermitian matrix from its upper triangle (column major, ns x ns): the lower
+// triangle becomes the conjugate mirror, the diagonal loses its imaginary part.
+__global__ __launch_bounds__(256) void zherm_upper_kernel(double2* __restrict__ C, int ns) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ns * ns) return;
+  const int j = (int)(e / ns), i = (int)(e % ns);
+  if (i > j) return;
+  double2 u = C[e];
+  if (i == j) {
+    C[e] = make_double2(u.x, 0.0);
+  } else {
+    C[(int64_t)i * ns + j] = make_double2(u.x, -u.y);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s) {
+  if (a.nd <= 0 || ns <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.nd + 255) / 256), (unsigned)ns);
+  hipLaunchKernelGGL(zhx_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s) {
+  if (a.n_atoms <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zproject_kernel, dim3((unsigned)a.n_atoms, (unsigned)ns), dim3(kZThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s) {
+  if (a.n_pts <= 0 || ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zscatter_kernel, dim3((unsigned)((a.n_pts + 255) / 256), (unsigned)ns), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zherm_upper(double2* C, int ns, hipStream_t s) {
+  const int64_t n2 = (int64_t)ns * ns;
+  hipLaunchKernelGGL(zherm_upper_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, C, ns);
+  return hipGetLastError();
+}
+
+}  // namespace chefsi
