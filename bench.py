@@ -255,6 +255,56 @@ def forces_figures(cs, prob, cfg, precision: str):
     return {"ms": ms, "atoms": int(f.shape[0]), "orbitals": ns, "max_abs_force": float(np.abs(f).max())}
 
 
+def kpoint_figures(cs, prob, cfg):
+    """The workload's grid, atoms and Ns at the Bloch wavevector k_d = pi / (2 L_d) in
+    complex FP64 (outside the timed steps): step rate and the rate of one H_k application
+    (projector gather + Bloch-phased stencil + scatter, HIP events on the launch stream)."""
+    import torch
+    from paper_2302_09708_amd import inputs
+    ns, m = cfg.ns, cfg.degree
+    k = tuple(np.pi / (2.0 * prob.n[d] * prob.h[d]) for d in range(3))
+    img = inputs.support_images(prob)
+    hr = cs.Handle(prob, precision=cs.FP64, max_ns=1)
+    lo, cut, hi = hr.chefsi_spectral_bounds()
+    hr.close()
+    h = cs.KPoint(prob, k, img, max_ns=ns)
+    ws = h.workspace(ns)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(cfg.x_seed + 3)
+    X = torch.randn((ns, prob.nd), generator=g, device="cuda", dtype=torch.complex128)
+    Y = torch.empty_like(X)
+    h.apply_h(X, Y, ns, ws)
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    b.record()
+    for _ in range(reps):
+        h.apply_h(X, Y, ns, ws)
+    e.record()
+    torch.cuda.synchronize()
+    apply_ms = b.elapsed_time(e) / reps
+    del Y
+    d = h.step(X, ns, m, lo, cut, hi, ws)  # warm-up step
+    lo, cut = d[0], d[-1]
+    steps = 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        d = h.step(X, ns, m, lo, cut, hi, ws)
+        lo, cut = d[0], d[-1]
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / steps
+    h.close()
+    del X, ws
+    torch.cuda.empty_cache()
+    # algorithmic bytes of one application: read X, write Y (16 B each per point and
+    # orbital), Veff once, the projector values and alpha (small)
+    apply_bytes = prob.nd * ns * 32.0 + prob.nd * 8.0
+    gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
+    return {"k_bohr_inv": list(k), "dtype": "c128", "iter_per_s": 1e3 / step_ms, "ms_per_step": step_ms,
+            "apply_h_ms": apply_ms, "apply_h_gbs": gbs, "apply_h_frac": gbs / HBM_PEAK_GBS,
+            "ritz_lowest": float(d[0])}
+
+
 def copy_gbs():
     """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes / time), the
     practical streaming ceiling the stencil's rate is also compared with."""
@@ -363,6 +413,7 @@ def main():
 
     lz = lanczos_figures(cs, prob, cfg, precision)
     fo = forces_figures(cs, prob, cfg, precision) if prob.n_atoms > 0 else None
+    kp = kpoint_figures(cs, prob, cfg) if cfg.name in ("cfg1", "cfg2") else None
     cgbs = copy_gbs()
     kern = main_run["kernels"]
     # the dominant kernel among those with a roofline (the FP64 dense stage and copies have none)
@@ -409,6 +460,7 @@ def main():
         "solve_ms": main_run["solve_ms"],
         "lanczos_lam_nd": lz,
         "nonlocal_forces": fo,
+        "kpoint": kp,
     }
     if other is not None:
         out["compare"] = {
