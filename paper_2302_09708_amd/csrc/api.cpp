@@ -1858,7 +1858,9 @@ struct chefsi_kpoint {
 namespace {
 
 struct ZLayout {
-  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, solver = 0, total = 0, solver_bytes = 0;
+  size_t bufB = 0, alpha = 0, hs = 0, ms = 0, d = 0, e = 0, info = 0, partial = 0, solver = 0, total = 0,
+         solver_bytes = 0;
+  BlasGram kg;  // K chunks of the projection (same split rule as the real FP64 Gram)
 };
 
 size_t zsolver_workspace(chefsi_kpoint* h, int ns) {
@@ -1889,6 +1891,12 @@ size_t zsolver_workspace(chefsi_kpoint* h, int ns) {
   query([&] {
     rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr, nullptr);
   });
+  const BlasGram kg = plan_blas_gram(h->nd, ns);
+  query([&] {
+    rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns,
+                                  (rocblas_int)kg.kc, &one, nullptr, ld, kg.kc, nullptr, ld, kg.kc, &one, nullptr, ns,
+                                  (rocblas_stride)ns * ns, kg.splits);
+  });
   query([&] {
     rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one, nullptr,
                   ld, nullptr, ld, &one, nullptr, ns);
@@ -1918,6 +1926,9 @@ ZLayout zlayout(chefsi_kpoint* h, int ns) {
   off += align256((size_t)ns * 8);
   L.info = off;
   off += 256;
+  L.kg = plan_blas_gram(h->nd, ns);
+  L.partial = off;
+  off += align256((size_t)L.kg.nparts * ns * ns * 16);
   L.solver = off;
   L.solver_bytes = zsolver_workspace(h, ns);
   off += align256(std::max<size_t>(L.solver_bytes, 256));
@@ -2269,12 +2280,23 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
     BLAS_TRY(rocblas_set_workspace(h->blas, zat<void>(ws, L.solver), std::max<size_t>(L.solver_bytes, 256)));
     auto zc = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
     auto zm = [](double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
-    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one,
-                           zc(Xf), ld, zc(Yf), ld, &zero, zm(Hs), ns));
-    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one,
-                           zc(Xf), ld, zc(Xf), ld, &zero, zm(Ms), ns));
-    HIP_TRY(launch_zherm_upper(Hs, ns, s));
-    HIP_TRY(launch_zherm_upper(Ms, ns, s));
+    // split-K: K chunks as one strided batch of products, partials summed in a fixed order
+    double2* part = zat<double2>(ws, L.partial);
+    const BlasGram& kg = L.kg;
+    auto gram = [&](const double2* A, const double2* Bm, double2* C) {
+      BLAS_TRY(rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none,
+                                             ns, ns, (rocblas_int)kg.kc, &one, zc(A), ld, kg.kc, zc(Bm), ld, kg.kc,
+                                             &zero, zm(part), ns, (rocblas_stride)ns * ns, kg.splits));
+      if (kg.tail > 0) {
+        const int64_t k0 = kg.kc * kg.splits;
+        BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns,
+                               (rocblas_int)kg.tail, &one, zc(A + k0), ld, zc(Bm + k0), ld, &zero,
+                               zm(part + (size_t)kg.splits * ns * ns), ns));
+      }
+      HIP_TRY(launch_zsum_partials(part, kg.nparts, ns, C, s));
+    };
+    gram(Xf, Yf, Hs);
+    gram(Xf, Xf, Ms);
     // Hermitian-definite eigenproblem (Alg. 1, Diagonalization)
     BLAS_TRY(rocsolver_zpotrf(h->blas, rocblas_fill_upper, ns, zm(Ms), ns, info));
     BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,

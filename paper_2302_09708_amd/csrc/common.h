@@ -303,6 +303,8 @@ struct ZNsArgs {
 hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s);
 hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s);
 hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s);
-hipError_t launch_zherm_upper(double2* C, int ns, hipStream_t s);
+// C = Hermitian completion of sum_q P_q (upper triangles read, fixed order), P: nparts
+// column-major ns x ns complex partial products.
+hipError_t launch_zsum_partials(const double2* P, int nparts, int ns, double2* C, hipStream_t s);
 
 }  // namespace chefsi

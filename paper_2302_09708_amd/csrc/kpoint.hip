@@ -121,22 +121,36 @@ __global__ __launch_bounds__(256) void zscatter_kernel(ZNsArgs a) {
   *o = cur;
 }
 
-// C <- Hermitian matrix from its upper triangle (column major, ns x ns): the lower
-// triangle becomes the conjugate mirror, the diagonal loses its imaginary part.
-__global__ __launch_bounds__(256) void zherm_upper_kernel(double2* __restrict__ C, int ns) {
+// C(i, j) = sum_q P_q(i, j) for i <= j in a fixed order (P_q column-major ns x ns), then the
+// Hermitian completion: C(j, i) = conj(C(i, j)), real diagonal.
+__global__ __launch_bounds__(256) void zsum_partials_kernel(const double2* __restrict__ P, int nparts, int ns,
+                                                            double2* __restrict__ C) {
+  const int64_t n2 = (int64_t)ns * ns;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)ns * ns) return;
+  if (e >= n2) return;
   const int j = (int)(e / ns), i = (int)(e % ns);
   if (i > j) return;
-  double2 u = C[e];
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < nparts; ++q) {
+    const double2 t = P[q * n2 + e];
+    re += t.x;
+    im += t.y;
+  }
   if (i == j) {
-    C[e] = make_double2(u.x, 0.0);
+    C[e] = make_double2(re, 0.0);
   } else {
-    C[(int64_t)i * ns + j] = make_double2(u.x, -u.y);
+    C[e] = make_double2(re, im);
+    C[(int64_t)i * ns + j] = make_double2(re, -im);
   }
 }
 
 }  // namespace
+
+hipError_t launch_zsum_partials(const double2* P, int nparts, int ns, double2* C, hipStream_t s) {
+  const int64_t n2 = (int64_t)ns * ns;
+  hipLaunchKernelGGL(zsum_partials_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, P, nparts, ns, C);
+  return hipGetLastError();
+}
 
 hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s) {
   if (a.nd <= 0 || ns <= 0) return hipSuccess;
@@ -154,12 +168,6 @@ hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s) {
 hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s) {
   if (a.n_pts <= 0 || ns <= 0) return hipSuccess;
   hipLaunchKernelGGL(zscatter_kernel, dim3((unsigned)((a.n_pts + 255) / 256), (unsigned)ns), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_zherm_upper(double2* C, int ns, hipStream_t s) {
-  const int64_t n2 = (int64_t)ns * ns;
-  hipLaunchKernelGGL(zherm_upper_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, C, ns);
   return hipGetLastError();
 }
 
