@@ -37,24 +37,67 @@ __device__ __forceinline__ double2 neighbour(const double2* __restrict__ xv, int
   return xv[i + (int64_t)p * stride];
 }
 
-__global__ __launch_bounds__(256) void zhx_kernel(ZHxArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.nd) return;
-  const int64_t v = blockIdx.y;
+constexpr int kZTx = 32, kZTy = 8;  // plane tile of one block (256 threads)
+constexpr int kZLx = kZTx + 2 * kMaxRadius, kZLy = kZTy + 2 * kMaxRadius;
+
+// x~ at (gx, gy) of plane z for any gx, gy within r of the grid: wrapped with the cell
+// phases in periodic directions, zero outside a Dirichlet boundary.
+__device__ __forceinline__ double2 plane_value(const double2* __restrict__ xv, int gx, int gy, int64_t zoff,
+                                               const ZHxArgs& a) {
+  double2 f = make_double2(1.0, 0.0);
+  const int g[2] = {gx, gy};
+  int w[2];
+  for (int d = 0; d < 2; ++d) {
+    const int n = a.n[d];
+    int c = g[d], k = 0;
+    while (c >= n) { c -= n; ++k; }
+    while (c < 0) { c += n; --k; }
+    if (k != 0) {
+      if (!a.per[d]) return make_double2(0.0, 0.0);
+      const double2 ph = k > 0 ? a.ph[d] : make_double2(a.ph[d].x, -a.ph[d].y);
+      for (int t = 0; t < (k > 0 ? k : -k); ++t) f = cmul(f, ph);
+    }
+    w[d] = c;
+  }
+  return cmul(xv[zoff + w[0] + (int64_t)a.n[0] * w[1]], f);
+}
+
+// One block per (32 x 8 tile of a plane, plane z, orbital): the tile and its r-wide x and y
+// halos are staged once in LDS (Bloch phases and Dirichlet zeros applied while staging),
+// the x and y neighbours come from LDS, the 2r z neighbours of every point from global
+// memory (through the caches).
+__global__ __launch_bounds__(kZTx * kZTy) void zhx_kernel(ZHxArgs a) {
+  __shared__ double2 tile[kZLy][kZLx];
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int tiles_x = (nx + kZTx - 1) / kZTx;
+  const int x0 = (blockIdx.x % tiles_x) * kZTx, y0 = (blockIdx.x / tiles_x) * kZTy;
+  const int z = blockIdx.y;
+  const int64_t v = blockIdx.z;
+  const int R = a.r;
+  const int64_t pstride = (int64_t)nx * ny;
   const double2* __restrict__ xv = a.x + v * a.nd;
-  const int nx = a.n[0], ny = a.n[1];
-  const int c[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((int64_t)nx * ny))};
-  const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
-  const double2 xi = xv[i];
+  const int tid = threadIdx.x;
+  const int lw = kZTx + 2 * R, lh = kZTy + 2 * R;
+  for (int e = tid; e < lw * lh; e += kZTx * kZTy) {
+    const int ly = e / lw, lx = e % lw;
+    tile[ly][lx] = plane_value(xv, x0 + lx - R, y0 + ly - R, pstride * z, a);
+  }
+  __syncthreads();
+  const int tx = tid % kZTx, ty = tid / kZTx;
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= nx || y >= ny) return;
+  const int64_t i = x + (int64_t)nx * y + pstride * z;
+  const double2 xi = tile[ty + R][tx + R];
   const double diag = a.c0 + a.veff[i] - a.sc;
   double re = diag * xi.x, im = diag * xi.y;
-  for (int d = 0; d < 3; ++d) {
-    for (int p = 1; p <= a.r; ++p) {
-      const double2 up = neighbour(xv, i, c[d], p, a.n[d], stride[d], a.per[d], a.ph[d]);
-      const double2 dn = neighbour(xv, i, c[d], -p, a.n[d], stride[d], a.per[d], a.ph[d]);
-      re += a.cw[d][p] * (up.x + dn.x);
-      im += a.cw[d][p] * (up.y + dn.y);
-    }
+  const double2* col = xv + x + (int64_t)nx * y;
+  for (int p = 1; p <= R; ++p) {
+    const double2 xu = tile[ty + R][tx + R + p], xd = tile[ty + R][tx + R - p];
+    const double2 yu = tile[ty + R + p][tx + R], yd = tile[ty + R - p][tx + R];
+    const double2 zu = neighbour(col, pstride * z, z, p, nz, pstride, a.per[2], a.ph[2]);
+    const double2 zd = neighbour(col, pstride * z, z, -p, nz, pstride, a.per[2], a.ph[2]);
+    re += a.cw[0][p] * (xu.x + xd.x) + a.cw[1][p] * (yu.x + yd.x) + a.cw[2][p] * (zu.x + zd.x);
+    im += a.cw[0][p] * (xu.y + xd.y) + a.cw[1][p] * (yu.y + yd.y) + a.cw[2][p] * (zu.y + zd.y);
   }
   double2 o = make_double2(a.sa * re, a.sa * im);
   if (a.prev != nullptr) {
@@ -154,8 +197,10 @@ hipError_t launch_zsum_partials(const double2* P, int nparts, int ns, double2* C
 
 hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s) {
   if (a.nd <= 0 || ns <= 0) return hipSuccess;
-  dim3 grid((unsigned)((a.nd + 255) / 256), (unsigned)ns);
-  hipLaunchKernelGGL(zhx_kernel, grid, dim3(256), 0, s, a);
+  if (a.r < 1 || a.r > kMaxRadius || a.n[2] > 65535) return hipErrorInvalidValue;
+  const int tiles = ((a.n[0] + kZTx - 1) / kZTx) * ((a.n[1] + kZTy - 1) / kZTy);
+  dim3 grid((unsigned)tiles, (unsigned)a.n[2], (unsigned)ns);
+  hipLaunchKernelGGL(zhx_kernel, grid, dim3(kZTx * kZTy), 0, s, a);
   return hipGetLastError();
 }
 
