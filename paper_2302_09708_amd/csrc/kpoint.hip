@@ -110,36 +110,53 @@ __global__ __launch_bounds__(kZTx * kZTy) void zhx_kernel(ZHxArgs a) {
 
 constexpr int kZThreads = 256;
 
-// one block per (atom, orbital); every thread sums its strided share of the support, then
+constexpr int kZProj = 4;  // projectors of an atom summed per pass over its support
+
+// one block per (atom, orbital); every thread sums its strided share of the support for
+// up to four projectors at once (each support value read once per four projectors), then
 // a fixed-shape tree sums the threads
 __global__ __launch_bounds__(kZThreads) void zproject_kernel(ZNlArgs a) {
-  __shared__ double2 red[kZThreads];
+  __shared__ double2 red[kZProj][kZThreads];
   const int J = blockIdx.x;
   const int64_t v = blockIdx.y;
   const int s0 = a.supp_off[J], nj = a.supp_off[J + 1] - s0;
   const int npj = a.nproj[J];
   const int64_t co = a.chi_off[J];
   const double2* __restrict__ xv = a.x + v * a.nd;
-  for (int q = 0; q < npj; ++q) {
-    double2 acc = make_double2(0.0, 0.0);
+  for (int q0 = 0; q0 < npj; q0 += kZProj) {
+    const int nq = min(kZProj, npj - q0);
+    double2 acc[kZProj];
+#pragma unroll
+    for (int u = 0; u < kZProj; ++u) acc[u] = make_double2(0.0, 0.0);
     for (int s = threadIdx.x; s < nj; s += kZThreads) {
-      const double2 t = cmulc(a.chi[co + (int64_t)q * nj + s], xv[a.supp_idx[s0 + s]]);
-      acc.x += t.x;
-      acc.y += t.y;
+      const double2 xs = xv[a.supp_idx[s0 + s]];
+#pragma unroll
+      for (int u = 0; u < kZProj; ++u) {
+        if (u < nq) {
+          const double2 t = cmulc(a.chi[co + (int64_t)(q0 + u) * nj + s], xs);
+          acc[u].x += t.x;
+          acc[u].y += t.y;
+        }
+      }
     }
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int u = 0; u < kZProj; ++u) red[u][threadIdx.x] = acc[u];
     __syncthreads();
     for (int w = kZThreads / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) {
-        red[threadIdx.x].x += red[threadIdx.x + w].x;
-        red[threadIdx.x].y += red[threadIdx.x + w].y;
+#pragma unroll
+        for (int u = 0; u < kZProj; ++u) {
+          red[u][threadIdx.x].x += red[u][threadIdx.x + w].x;
+          red[u][threadIdx.x].y += red[u][threadIdx.x + w].y;
+        }
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      const int col = a.poff[J] + q;
+    if ((int)threadIdx.x < nq) {
+      const int u = threadIdx.x;
+      const int col = a.poff[J] + q0 + u;
       const double g = a.gdv[col];
-      a.alpha[v * a.np_tot + col] = make_double2(g * red[0].x, g * red[0].y);
+      a.alpha[v * a.np_tot + col] = make_double2(g * red[u][0].x, g * red[u][0].y);
     }
     __syncthreads();
   }
