@@ -162,23 +162,39 @@ __global__ __launch_bounds__(kZThreads) void zproject_kernel(ZNlArgs a) {
   }
 }
 
-// one thread per (support point, orbital); every point is written by one thread
-__global__ __launch_bounds__(256) void zscatter_kernel(ZNsArgs a) {
+constexpr int kZScatV = 4;  // orbitals per scatter thread (the point's entries read once)
+
+// one thread per (support point, four orbitals); every output element is written by one thread
+__global__ __launch_bounds__(256) void zscatter_kernel(ZNsArgs a, int ns) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= a.n_pts) return;
-  const int64_t v = blockIdx.y;
-  const double2* __restrict__ al = a.alpha + v * a.np_tot;
-  double2 acc = make_double2(0.0, 0.0);
+  const int64_t v0 = (int64_t)blockIdx.y * kZScatV;
+  const int nv = (int)min((int64_t)kZScatV, (int64_t)ns - v0);
+  double2 acc[kZScatV];
+#pragma unroll
+  for (int u = 0; u < kZScatV; ++u) acc[u] = make_double2(0.0, 0.0);
   for (int e = a.ptr[p]; e < a.ptr[p + 1]; ++e) {
-    const double2 t = cmul(a.val[e], al[a.col[e]]);
-    acc.x += t.x;
-    acc.y += t.y;
+    const double2 c = a.val[e];
+    const int q = a.col[e];
+#pragma unroll
+    for (int u = 0; u < kZScatV; ++u) {
+      if (u < nv) {
+        const double2 t = cmul(c, a.alpha[(v0 + u) * a.np_tot + q]);
+        acc[u].x += t.x;
+        acc[u].y += t.y;
+      }
+    }
   }
-  double2* o = a.out + v * a.nd + a.pt[p];
-  double2 cur = *o;
-  cur.x += a.sa * acc.x;
-  cur.y += a.sa * acc.y;
-  *o = cur;
+#pragma unroll
+  for (int u = 0; u < kZScatV; ++u) {
+    if (u < nv) {
+      double2* o = a.out + (v0 + u) * a.nd + a.pt[p];
+      double2 cur = *o;
+      cur.x += a.sa * acc[u].x;
+      cur.y += a.sa * acc[u].y;
+      *o = cur;
+    }
+  }
 }
 
 // C(i, j) = sum_q P_q(i, j) for i <= j in a fixed order (P_q column-major ns x ns), then the
@@ -229,7 +245,8 @@ hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s) {
 
 hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s) {
   if (a.n_pts <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zscatter_kernel, dim3((unsigned)((a.n_pts + 255) / 256), (unsigned)ns), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(zscatter_kernel, dim3((unsigned)((a.n_pts + 255) / 256), (unsigned)((ns + kZScatV - 1) / kZScatV)),
+                     dim3(256), 0, s, a, ns);
   return hipGetLastError();
 }
 
