@@ -37,7 +37,7 @@ __device__ __forceinline__ double2 neighbour(const double2* __restrict__ xv, int
   return xv[i + (int64_t)p * stride];
 }
 
-constexpr int kZTx = 32, kZTy = 8;  // plane tile of one block (256 threads)
+constexpr int kZTx = 32, kZTy = 16;  // plane tile of one block (512 threads)
 constexpr int kZLx = kZTx + 2 * kMaxRadius, kZLy = kZTy + 2 * kMaxRadius;
 
 // x~ at (gx, gy) of plane z for any gx, gy within r of the grid: wrapped with the cell
@@ -62,7 +62,7 @@ __device__ __forceinline__ double2 plane_value(const double2* __restrict__ xv, i
   return cmul(xv[zoff + w[0] + (int64_t)a.n[0] * w[1]], f);
 }
 
-// One block per (32 x 8 tile of a plane, plane z, orbital): the tile and its r-wide x and y
+// One block per (32 x 16 tile of a plane, plane z, orbital): the tile and its r-wide x and y
 // halos are staged once in LDS (Bloch phases and Dirichlet zeros applied while staging),
 // the x and y neighbours come from LDS, the 2r z neighbours of every point from global
 // memory (through the caches).
