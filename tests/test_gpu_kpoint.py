@@ -1,7 +1,8 @@
 """Parity of the complex (Bloch wavevector) path with the complex FP64 oracle through the
-C-ABI: H_k X element by element (1e-12 of max |H_k X|), one CheFSI step (Ritz values to
-1e-10 relative, the rotated subspace to 1e-8), convergence to the dense spectrum of H_k,
-k = 0 against the real handle, and bitwise repeatability."""
+C-ABI: H_k X element by element (1e-12 of max |H_k X|) on small grids and on sampled
+columns at the bench's full size, one CheFSI step (Ritz values to 1e-10 relative, the
+rotated subspace to 1e-8), convergence to the dense spectrum of H_k, k = 0 against the real
+handle, argument errors, and bitwise repeatability."""
 import numpy as np
 import pytest
 
@@ -91,7 +92,6 @@ def test_step_matches_oracle(cs, case):
     img = inputs.support_images(prob)
     ns, degree = 16, 8
     x = _block(prob.nd, ns, 2)
-    ev = None
     lo, cut, hi = -3.0, 2.0, 200.0
     d_ref, x_ref = ok.chefsi_step_k(prob, img, k, x, degree, lo, cut, hi)
     h = cs.KPoint(prob, k, img, max_ns=ns)
@@ -111,7 +111,6 @@ def test_step_matches_oracle(cs, case):
     d2 = h.step(X2, ns, degree, lo, cut, hi, ws)
     assert np.array_equal(d, d2) and torch.equal(X, X2)
     h.close()
-    del ev
 
 
 def test_steps_converge_to_dense_spectrum(cs):
@@ -119,7 +118,7 @@ def test_steps_converge_to_dense_spectrum(cs):
                                 nproj_per_atom=4, seed=24)
     img = inputs.support_images(prob)
     k = (0.6, -0.2, 0.9)
-    ev = np.linalg.eigvalsh(ok.dense_h_k(prob, img, k)) if prob.nd <= 4096 else None
+    ev = np.linalg.eigvalsh(ok.dense_h_k(prob, img, k))
     ns = 20
     h = cs.KPoint(prob, k, img, max_ns=ns)
     ws = h.workspace(ns)
@@ -151,4 +150,31 @@ def test_bad_arguments(cs):
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(cs.ChefsiError):
         h.apply_h(X, torch.zeros_like(X), 4, small)
+    h.close()
+
+
+def test_apply_h_full_size_sampled(cs):
+    """The bench's k-point configuration (72^3 grid, 128 atoms x 4 projectors, Ns = 600,
+    k_d = pi / (2 L_d)), sampled: three columns of H_k X against the oracle, which acts on
+    each column alone."""
+    prob = inputs.make_problem(inputs.CONFIGS["cfg2"])
+    img = inputs.support_images(prob)
+    k = tuple(np.pi / (2.0 * prob.n[d] * prob.h[d]) for d in range(3))
+    ns = 600
+    h = cs.KPoint(prob, k, img, max_ns=ns)
+    ws = h.workspace(ns)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    X = torch.randn((ns, prob.nd), generator=g, device="cuda", dtype=torch.complex128)
+    Y = torch.empty_like(X)
+    print(f"apply_h full size n={prob.n} ns={ns}", flush=True)
+    h.apply_h(X, Y, ns, ws)
+    torch.cuda.synchronize()
+    for j in (0, 299, 599):
+        x = X[j].cpu().numpy()
+        ref = ok.apply_h_k(prob, img, k, x[:, None])[:, 0]
+        y = Y[j].cpu().numpy()
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        print(f"  column {j}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-12
     h.close()
