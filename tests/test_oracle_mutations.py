@@ -9,9 +9,11 @@ import pytest
 
 import oracle.chefsi as oc
 import oracle.hamiltonian as oh
+import oracle.kpoint as ok
 from oracle.fd import second_derivative_weights
 from tests import test_oracle_chefsi as tc
 from tests import test_oracle_hamiltonian as th
+from tests import test_oracle_kpoint as tk
 
 
 def _kinetic_wrong_index(prob, x):
@@ -107,3 +109,45 @@ def test_diagonalize_mutant_is_caught(monkeypatch):
     monkeypatch.setattr(oc, "diagonalize", _diag_swapped_operands)
     with pytest.raises(AssertionError):
         tc.test_diagonalize_agrees_with_independent_routes()
+
+
+# ---- the complex (Bloch wavevector) oracle -------------------------------------------
+_orig_blocks_k = ok.projector_blocks_k
+_orig_bloch_shift = ok._bloch_shift
+
+
+def _projector_phase_conjugated(prob, img, k):
+    for idx, chi, gam in _orig_blocks_k(prob, img, k):
+        yield idx, chi.conj(), gam                  # planted: exp(-i k.mL) instead of exp(+i k.mL)
+
+
+def _projector_phase_dropped(prob, img, k):
+    for idx, chi, gam in _orig_blocks_k(prob, img, k):
+        yield idx, chi.real.astype(complex), gam    # planted: no Bloch phase on the projectors
+
+
+def _ghost_phase_conjugated(u, p, d, periodic, phase):
+    return _orig_bloch_shift(u, p, d, periodic, np.conj(phase))   # planted: wrong sign of k in the ghosts
+
+
+def _project_k_no_conjugate(prob, img, k, xf):
+    yf = ok.apply_h_k(prob, img, k, xf)
+    hs = xf.T @ yf                                  # planted: transpose without conjugation
+    ms = xf.conj().T @ xf
+    return 0.5 * (hs + hs.conj().T), 0.5 * (ms + ms.conj().T)
+
+
+KCASES = [
+    ("projector_blocks_k", _projector_phase_conjugated, tk.test_supercell_folds_three_wavevectors),
+    ("projector_blocks_k", _projector_phase_dropped, tk.test_supercell_folds_three_wavevectors),
+    ("_bloch_shift", _ghost_phase_conjugated,
+     lambda: tk.test_bloch_plane_waves_have_the_fd_symbol((0.3, -0.2, 0.5), (1, 0, -2))),
+    ("project_k", _project_k_no_conjugate, tk.test_complex_step_converges_to_lowest_eigenvalues),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pin", KCASES, ids=[c[1].__name__ for c in KCASES])
+def test_kpoint_mutant_is_caught(monkeypatch, name, mutant, pin):
+    monkeypatch.setattr(ok, name, mutant)
+    with pytest.raises(AssertionError):
+        pin()
