@@ -12,7 +12,9 @@ Prints ONE JSON line with iterations/s, the roofline position of the dominant
 kernel (timed with HIP events recorded by the library on its launch stream),
 the other precision on the same inputs ("compare": FP64 vs mixed) and, at
 N = 1, the FP64 CPU oracle timed on a bounded sample of the same workload on
-this host's cores.
+this host's cores.  Figures outside the timed steps: the Lanczos estimate of
+lambda_Nd, the nonlocal forces, and (72^3 and 24^3 workloads) the same grid at
+a Bloch wavevector in complex FP64 ("kpoint").
 """
 from __future__ import annotations
 
