@@ -301,7 +301,8 @@ int chefsi_version(void);
  * (ns, Nd).  A step is Alg. 1 with conjugate transposes: Hs = X~^H H X~,
  * Ms = X~^H X~, Hs Z = Ms Z D (Hermitian definite, ascending D), X = X~ Z.
  * The handle holds its own copies of all host inputs (freed by
- * chefsi_kpoint_destroy); calls are ordered on their stream; max_ns <= 65535.
+ * chefsi_kpoint_destroy); calls are ordered on their stream; max_ns <= 65535 and
+ * Nd * max_ns < 2^31 (CHEFSI_ERR_INVALID_ARG otherwise).
  * Errors as for the real handle (INVALID_ARG, WORKSPACE, NOT_POSDEF, EIG,
  * NONFINITE, SOLVER, HIP, OOM); after an error the handle stays usable and X
  * is unspecified. */

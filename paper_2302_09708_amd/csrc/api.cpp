@@ -2083,6 +2083,8 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
     }
     check(nd < (int64_t)1 << 31, "Nd must be below 2^31");
     check(max_ns >= 1 && (int64_t)max_ns <= nd && max_ns <= 65535, "max_ns must satisfy 1 <= max_ns <= min(Nd, 65535)");
+    // the library products (zgemm) take the whole block at once: keep it below 2^31 elements
+    check(nd * max_ns < (int64_t)1 << 31, "k-point blocks of 2^31 or more elements (Nd * max_ns) are not supported");
     h->nd = nd;
     h->max_ns = max_ns;
     h->w = fd_weights(grid->fd_order);
