@@ -78,6 +78,42 @@ def nonlocal_energy(prob, psi: np.ndarray, occ: np.ndarray) -> float:
     return e
 
 
+def nonlocal_stress(prob, psi: np.ndarray, occ: np.ndarray, disp: np.ndarray) -> np.ndarray:
+    """Nonlocal (Kleinman-Bylander) component of the stress (3 x 3, Ha / bohr^3), the other
+    force-like quantity Sec. 2 evaluates with the gradient of the orbitals followed by the
+    projectors.  Under a homogeneous strain eps the cell, the grid and the atoms move with
+    (1 + eps), dV takes the factor det(1 + eps), the grid values of a normalised orbital the
+    factor det^-1/2, and every projector is sampled at the strained displacement
+    (1 + eps) d, d = r_i - R_J.  So
+
+        E_nl(eps) = det(1 + eps) sum_n g_n sum_{J,a} gamma_Ja (dV sum_i chi_Ja((1 + eps) d_i) psi_n,i)^2,
+
+    and d chi((1 + eps) d) / d eps_ab = (d_a chi)(d) d_b.  Integrating by parts over the
+    support (chi vanishes on its edge) turns sum_i (d_a chi) d_b psi into
+    -sum_i chi (delta_ab psi + d_b d_a psi), so sigma_ab = (1 / Omega) dE_nl / d eps_ab is
+
+        sigma_ab = -(1 / Omega) [delta_ab E_nl + 2 sum_n g_n sum_{J,a} gamma_Ja alpha_Ja,n beta_Ja,n;ab],
+        alpha = dV chi^T psi_n,   beta_ab = dV sum_i chi(i) d_b(i) (d psi_n / dx_a)(i),
+
+    with the FD gradient of the Laplacian's order (``gradient``) and Omega = Nd dV.
+    ``disp`` is (sum n_J, 3): d for every support point, in the order of ``supp_idx``."""
+    dv = prob.h[0] * prob.h[1] * prob.h[2]
+    psi = np.asarray(psi, dtype=np.float64)
+    disp = np.asarray(disp, dtype=np.float64).reshape(-1, 3)
+    omega = psi.shape[0] * dv
+    grads = [gradient(prob, psi, a) for a in range(3)]
+    e_nl = nonlocal_energy(prob, psi, occ)
+    s = np.zeros((3, 3))
+    for J, (idx, chi, gam) in enumerate(atom_blocks(prob)):
+        dJ = disp[int(prob.supp_ptr[J]):int(prob.supp_ptr[J + 1])]
+        alpha = dv * (chi.T @ psi[idx, :])                     # np_J x Ns
+        for a in range(3):
+            for b in range(3):
+                beta = dv * ((chi * dJ[:, b:b + 1]).T @ grads[a][idx, :])
+                s[a, b] += 2.0 * float(np.sum(gam[:, None] * occ[None, :] * alpha * beta))
+    return -(np.eye(3) * e_nl + s) / omega
+
+
 def kinetic_stress(prob, psi: np.ndarray, occ: np.ndarray) -> np.ndarray:
     """Electronic kinetic-energy component of the stress (3 x 3, Ha / bohr^3) from the FD
     gradient of the orbitals (Sec. 2 reuses that gradient for it):

@@ -251,6 +251,23 @@ def support_images(prob: Problem) -> np.ndarray:
     return out
 
 
+def support_displacements(prob: Problem) -> np.ndarray:
+    """(sum n_J, 3) float64: for every support point of atom J, its displacement from the
+    atom, r_i - R_J - m L (bohr), the minimum-image offset chi_J was evaluated at (m from
+    ``support_images``; plain r_i - R_J in Dirichlet directions)."""
+    nx, ny = prob.n[0], prob.n[1]
+    L = _box(prob.n, prob.h)
+    img = support_images(prob)
+    out = np.zeros((len(prob.supp_idx), 3), dtype=np.float64)
+    for J in range(prob.n_atoms):
+        lo, hi = int(prob.supp_ptr[J]), int(prob.supp_ptr[J + 1])
+        lin = np.asarray(prob.supp_idx[lo:hi], dtype=np.int64)
+        coords = (lin % nx, (lin // nx) % ny, lin // (nx * ny))
+        for d in range(3):
+            out[lo:hi, d] = coords[d] * prob.h[d] - prob.atoms[J][d] - img[lo:hi, d] * L[d]
+    return out
+
+
 def make_problem(cfg: Config) -> Problem:
     atoms = atom_positions(cfg)
     veff = gaussian_wells(cfg.n, cfg.h, cfg.bc, atoms)

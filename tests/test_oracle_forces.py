@@ -105,3 +105,116 @@ def test_kinetic_stress_of_plane_waves():
     got = kinetic_stress(prob, psi, np.array([g]))
     np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max())
     assert np.array_equal(got, got.T)
+
+
+def test_nonlocal_energy_is_the_expectation_of_vnl():
+    """E_nl = sum_n g_n psi_n^T (V_nl psi_n) dV, V_nl the oracle's (pinned) nonlocal operator:
+    ties the energy the forces are differentiated from to the operator inside H, so a dV or
+    gamma slip made in the force/energy code alone fails here."""
+    from oracle.hamiltonian import nonlocal_potential
+    from paper_2302_09708_amd import inputs
+    prob = inputs.small_problem(n=(16, 15, 14), n_atoms=12, nproj_per_atom=4, seed=5)  # overlapping supports
+    prob.gamma = prob.gamma * np.linspace(0.5, 1.5, len(prob.gamma))                     # distinct energies
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((prob.nd, 5))
+    occ = np.array([2.0, 2.0, 1.3, 0.4, 0.0])
+    dv = prob.h[0] * prob.h[1] * prob.h[2]
+    ref = float(np.sum(occ * np.einsum("ij,ij->j", psi, nonlocal_potential(prob, psi)))) * dv
+    assert nonlocal_energy(prob, psi, occ) == pytest.approx(ref, rel=1e-13)
+
+
+def test_nonlocal_energy_of_a_constant_projector():
+    """One projector equal to 1/sqrt(Nd dV) on every point (unit norm): a constant orbital c has
+    E_nl = gamma g c^2 Nd dV; a plane wave orthogonal to the constant has none."""
+    n, h = (8, 6, 10), (0.3, 0.35, 0.25)
+    nd = int(np.prod(n))
+    dv = h[0] * h[1] * h[2]
+    gam = 0.8
+    prob = bare_problem(n, h, (0, 0, 0), 4, atoms=[(np.arange(nd), np.full((nd, 1), 1 / np.sqrt(nd * dv)), [gam])])
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    c = 0.37
+    psi = np.stack([np.full(nd, c), np.cos(2 * np.pi * x / n[0]).reshape(-1)], axis=1)
+    occ = np.array([1.5, 2.0])
+    assert nonlocal_energy(prob, psi, occ) == pytest.approx(gam * 1.5 * c * c * nd * dv, rel=1e-13)
+    assert nonlocal_energy(prob, psi[:, 1:], occ[1:]) == pytest.approx(0.0, abs=1e-25)
+
+
+def _gaussian_atom_at(n, h, R, strain=None, sigma=0.45):
+    """s + p Gaussians of an atom at R on the whole periodic grid, sampled at the displacement
+    (1 + strain) d (minimum image d); returns (idx, chi, gamma, d)."""
+    L = np.array(n) * np.array(h)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    r = [x.reshape(-1) * h[0], y.reshape(-1) * h[1], z.reshape(-1) * h[2]]
+    d = np.stack([(r[k] - R[k] + 0.5 * L[k]) % L[k] - 0.5 * L[k] for k in range(3)], axis=1)
+    ds = d if strain is None else d @ (np.eye(3) + strain).T
+    g = np.exp(-(ds ** 2).sum(axis=1) / (2 * sigma ** 2))
+    chi = np.stack([g, ds[:, 0] / sigma * g, ds[:, 1] / sigma * g, ds[:, 2] / sigma * g], axis=1)
+    return np.arange(len(g)), chi, [0.7, -0.3, 0.45, 0.2], d
+
+
+def test_nonlocal_stress_is_the_strain_derivative_of_the_energy():
+    """sigma_ab = (1 / Omega) dE_nl / d eps_ab, E_nl(eps) = det(1 + eps) E_nl[chi sampled at
+    (1 + eps) d, psi values fixed] (dV scales by det, a normalised orbital's values by
+    det^-1/2): the FD-gradient formula against a central difference of the energy in every
+    component, on band-limited orbitals and two atoms."""
+    from oracle.forces import nonlocal_stress
+    n, h, order = (28, 26, 30), (0.2, 0.21, 0.19), 12
+    rng = np.random.default_rng(21)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ph = [2 * np.pi * x / n[0], 2 * np.pi * y / n[1], 2 * np.pi * z / n[2]]
+    ns = 3
+    psi = np.zeros((x.size, ns))
+    for j in range(ns):
+        f = np.zeros(x.shape)
+        for kx in range(-2, 3):
+            for ky in range(-2, 3):
+                for kz in range(-2, 3):
+                    a, b = rng.standard_normal(2)
+                    t = kx * ph[0] + ky * ph[1] + kz * ph[2]
+                    f += a * np.cos(t) + b * np.sin(t)
+        psi[:, j] = f.reshape(-1)
+    occ = np.array([2.0, 1.5, 0.5])
+    atoms = [np.array([2.31, 2.57, 2.93]), np.array([3.9, 1.2, 4.1])]
+    omega = x.size * h[0] * h[1] * h[2]
+
+    def energy(strain):
+        blocks = [_gaussian_atom_at(n, h, R, strain) for R in atoms]
+        prob = bare_problem(n, h, (0, 0, 0), order, atoms=[b[:3] for b in blocks])
+        return np.linalg.det(np.eye(3) + strain) * nonlocal_energy(prob, psi, occ)
+
+    blocks = [_gaussian_atom_at(n, h, R) for R in atoms]
+    prob = bare_problem(n, h, (0, 0, 0), order, atoms=[b[:3] for b in blocks])
+    disp = np.concatenate([b[3] for b in blocks])
+    sig = nonlocal_stress(prob, psi, occ, disp)
+    delta = 1e-5
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = delta
+            fd = (energy(e) - energy(-e)) / (2 * delta) / omega
+            assert sig[a, b] == pytest.approx(fd, abs=1e-6 * np.abs(sig).max())
+    # the p energies differ, so the projector set is not rotation invariant and sigma is not
+    # symmetric: the check above also fixes which index is the gradient's
+    assert np.abs(sig - sig.T).max() >= 1e-2 * np.abs(sig).max()
+
+
+def test_support_displacements_match_the_projector_offsets():
+    """The generator's displacements reproduce chi: the s projector of every atom is a Gaussian
+    of |d| (common normalisation), and |d| <= rc."""
+    from paper_2302_09708_amd import inputs
+    for bc in ((0, 0, 0), (0, 0, 1)):
+        prob = inputs.small_problem(n=(14, 13, 20), bc=bc, n_atoms=4, nproj_per_atom=4, seed=9)
+        d = inputs.support_displacements(prob)
+        r2 = (d ** 2).sum(axis=1)
+        assert r2.max() <= inputs.PROJ_RC ** 2 + 1e-12
+        for J in range(prob.n_atoms):
+            lo, hi = int(prob.supp_ptr[J]), int(prob.supp_ptr[J + 1])
+            nj = hi - lo
+            chi = prob.chi[4 * lo:4 * hi].reshape(4, nj)        # s, px, py, pz rows of atom J
+            ratio = chi[0] / np.exp(-r2[lo:hi] / (2 * inputs.PROJ_SIGMA ** 2))
+            np.testing.assert_allclose(ratio, ratio[0], rtol=1e-12)
+            for k in range(3):                                   # p_k / s = const * d_k
+                sel = np.abs(d[lo:hi, k]) > 0.1
+                q = chi[1 + k][sel] / chi[0][sel] / d[lo:hi, k][sel]
+                np.testing.assert_allclose(q, q[0], rtol=1e-10)
+                np.testing.assert_allclose(chi[1 + k][~sel] / chi[0][~sel], q[0] * d[lo:hi, k][~sel], atol=1e-10)
