@@ -136,6 +136,20 @@ int chefsi_workspace_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes);
  * chefsi_workspace_bytes() this is a request's whole device footprint. */
 int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
 
+/* Tiling of the fused stencil pass (Sec. 2.1; the paper tiles the stencil for its GPU, this
+ * library picks its own tiling at create from the grid shape).  A block of the pass covers
+ * whole x rows: row_groups groups of threads, each thread rows_per_thread consecutive rows,
+ * so a tile is row_groups * rows_per_thread rows; threads = nx * row_groups (at most 1024
+ * for one row per thread, 512 otherwise).  chefsi_set_stencil_tiling(h, 0, 0) restores the
+ * library's choice; another pair replaces it (the projector records are rebuilt) and
+ * returns CHEFSI_ERR_INVALID_ARG, keeping the current tiling, when it does not fit the
+ * grid (rows_per_thread 1..4).  Results do not depend on the tiling: every point sums its
+ * stencil, potential and projector terms in the same order.  For tuning and tests.
+ * chefsi_get_stencil_tiling writes {rows_per_thread, row_groups, tile rows, halo values
+ * per thread} to tiling[0..3]. */
+int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups);
+int chefsi_get_stencil_tiling(const chefsi_handle_t* h, int32_t* tiling);
+
 /* Rigorous filter bounds for the first step (the paper names lam_hi the
  * largest eigenvalue of H and lam_cut the cutoff, Alg. 1, but does not say how
  * they are obtained; these are this library's reading):

@@ -43,6 +43,7 @@ EXPORTS = (
     "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
     "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
     "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
+    "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling",
 )
 
 
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.chefsi_destroy.restype = None
     lib.chefsi_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_handle_bytes.argtypes = [vp, C.POINTER(sz)]
+    lib.chefsi_set_stencil_tiling.argtypes = [vp, i32, i32]
+    lib.chefsi_get_stencil_tiling.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
     lib.chefsi_update_veff.argtypes = [vp, pd, vp]
@@ -299,6 +302,14 @@ class Handle:
 
     def device_bytes(self) -> int:
         return self.chefsi_handle_bytes()
+
+    def chefsi_set_stencil_tiling(self, rows_per_thread: int, row_groups: int) -> None:
+        self._check(self._lib.chefsi_set_stencil_tiling(self.h, rows_per_thread, row_groups))
+
+    def chefsi_get_stencil_tiling(self) -> Tuple[int, int, int, int]:
+        t = (C.c_int32 * 4)()
+        self._check(self._lib.chefsi_get_stencil_tiling(self.h, t))
+        return tuple(int(v) for v in t)
 
     def chefsi_spectral_bounds(self) -> Tuple[float, float, float]:
         lo, cut, hi = C.c_double(), C.c_double(), C.c_double()

@@ -128,10 +128,14 @@ struct chefsi_handle {
   double* pinned = nullptr;
   int n_pts = 0;     // scatter records
   int n_hxrec = 0;   // stencil-pass records
+  size_t hx_rec_bytes = 0;   // device bytes of the stencil-pass records
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
-  int py_override = 0;
+  // point-major projector table (host): point i lists pt_col/pt_val[pt_cnt[i] .. pt_cnt[i+1]),
+  // kept so the stencil-pass records can be rebuilt for another tiling
+  std::vector<int> pt_cnt, pt_col;
+  std::vector<double> pt_val;
 
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
@@ -508,7 +512,7 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
   a.sb = TC(sb);
   {
     ProfScope ps(h, P_HX, s);
-    const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->py_override);
+    const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], ns, h->radius, (int)sizeof(TI), h->hx_plan.py, h->hx_plan.nyg);
     if (!p.ok || p.ty != h->hx_plan.ty)
       throw Error{CHEFSI_ERR_HIP, "stencil tiling differs from the one the projector records were built for"};
     HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
@@ -954,6 +958,79 @@ T* upload(chefsi_handle* h, const T* src, size_t n) {
   return d;
 }
 
+// Stencil-pass projector records for tiling hp (points in one to four projector entries,
+// grouped by (y tile, z plane); at most ty * nx per group <= PY * threads), replacing the
+// handle's current ones.  The LDS budget is checked for the longest z chunk (zc = nz),
+// which the planner picks for wide blocks.
+void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
+  const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+  const int64_t nd = h->nd;
+  HxPlan worst = hp;
+  worst.zc = nz;
+  const size_t lds_need = std::max(hx_lds_bytes(worst, nx, h->radius, h->precision == CHEFSI_FP64 ? 8 : 4,
+                                                h->np_tot, 8),
+                                   hx_lds_bytes(worst, nx, h->radius, 4, h->np_tot, 8));
+  check(lds_need <= kHxMaxLds, "too many projectors for the stencil pass (alpha row does not fit in LDS)");
+  const int64_t nkeys = (int64_t)hp.nty * nz;
+  auto key_of = [&](int64_t i) {
+    const int y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+    return (int64_t)(y / hp.ty) * nz + z;
+  };
+  const std::vector<int>& cnt = h->pt_cnt;
+  std::vector<int> rptr(nkeys + 1, 0);
+  for (int64_t i = 0; i < nd; ++i) {
+    const int n = cnt[i + 1] - cnt[i];
+    if (n >= 1 && n <= 4) rptr[key_of(i) + 1] += 1;
+  }
+  for (int64_t k = 0; k < nkeys; ++k) rptr[k + 1] += rptr[k];
+  const int nrec = rptr[nkeys];
+  std::vector<HxRec<double>> r64(std::max(nrec, 1));
+  std::vector<HxRec<float>> r32(std::max(nrec, 1));
+  std::memset(r64.data(), 0, r64.size() * sizeof(HxRec<double>));
+  std::memset(r32.data(), 0, r32.size() * sizeof(HxRec<float>));
+  std::vector<int> rfill(rptr.begin(), rptr.end() - 1);
+  for (int64_t i = 0; i < nd; ++i) {
+    const int b = cnt[i], n = cnt[i + 1] - b;
+    if (n < 1 || n > 4) continue;
+    const int r = rfill[key_of(i)]++;
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny);
+    int col[4] = {0, 0, 0, 0};
+    for (int k = 0; k < n; ++k) {
+      col[k] = h->pt_col[b + k];
+      r64[r].val[k] = h->pt_val[b + k];
+      r32[r].val[k] = (float)h->pt_val[b + k];
+    }
+    r64[r].lidx = r32[r].lidx = (y % hp.ty) * nx + x;
+    r64[r].c01 = r32[r].c01 = col[0] | (col[1] << 16);
+    r64[r].c23 = r32[r].c23 = col[2] | (col[3] << 16);
+  }
+  int* nptr = nullptr;
+  HxRec<double>* n64 = nullptr;
+  HxRec<float>* n32 = nullptr;
+  try {
+    if (nrec > 0) {
+      nptr = upload(h, rptr.data(), rptr.size());
+      n64 = upload(h, r64.data(), r64.size());
+      n32 = upload(h, r32.data(), r32.size());
+    }
+  } catch (...) {
+    for (void* q : {(void*)nptr, (void*)n64, (void*)n32})
+      if (q) (void)hipFree(q);
+    throw;
+  }
+  for (void* q : {(void*)h->hx_rec_ptr, (void*)h->hx_rec64, (void*)h->hx_rec32})
+    if (q) (void)hipFree(q);
+  h->device_bytes -= h->hx_rec_bytes;
+  h->hx_rec_bytes = nrec > 0 ? rptr.size() * sizeof(int) + r64.size() * sizeof(HxRec<double>) +
+                                   r32.size() * sizeof(HxRec<float>)
+                             : 0;
+  h->hx_rec_ptr = nptr;
+  h->hx_rec64 = n64;
+  h->hx_rec32 = n32;
+  h->n_hxrec = nrec;
+  h->hx_plan = hp;
+}
+
 void release(chefsi_handle* h) {
   void* ptrs[] = {h->veff64, h->veff32, h->supp_off, h->supp_idx, h->chi_off,  h->nproj,    h->poff,
                   h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->rec,      h->ent_col,  h->hx_rec_ptr,
@@ -1044,7 +1121,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     check(grid->n[0] <= kHxMaxThreads, "nx above 512 is not supported by the stencil tiling");
     check(max_ns >= 1 && (int64_t)max_ns <= nd, "max_ns must satisfy 1 <= max_ns <= Nd");
     for (int eb : {4, 8})
-      check(plan_hx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2, eb, 0).ok,
+      check(plan_hx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2, eb, 0, 0).ok,
             "grid too wide in x for the stencil tiling (needs 2r*nx <= 4*blocksize)");
     h->nd = nd;
     h->max_ns = max_ns;
@@ -1090,8 +1167,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     // the dense stage must give the same bits whatever else runs on the device (results of
     // a request alone and among others are compared bit for bit): no atomics in rocBLAS
     BLAS_TRY(rocblas_set_atomics_mode(h->blas, rocblas_atomics_not_allowed));
-    if (const char* e = std::getenv("CHEFSI_HX_PY")) h->py_override = std::atoi(e);  // tiling only
-    h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->py_override);
+    h->hx_plan = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, precision == CHEFSI_FP64 ? 8 : 4, 0, 0);
     check(h->hx_plan.ok, "no stencil tiling fits this grid");
 
     if (hipHostMalloc((void**)&h->pinned, (size_t)max_ns * sizeof(double) + 64, hipHostMallocDefault) != hipSuccess) {
@@ -1138,58 +1214,23 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
           }
         }
       }
-      // points with at most four entries: one stencil-pass record each, grouped by
-      // (y tile, z plane) of the tiling (at most ty*nx per group <= PY * threads);
-      // points with more: one scatter record {point, first entry, entry count, 0} each,
-      // entries in atom order padded with zeros to a multiple of 4
-      const HxPlan& hp = h->hx_plan;
-      const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+      h->pt_cnt = std::move(cnt);
+      h->pt_col = std::move(eproj);
+      h->pt_val = std::move(eval);
       check(h->np_tot < 65536, "more than 65535 projectors");
-      const size_t lds_need = std::max(
-          hx_lds_bytes(hp, nx, h->radius, precision == CHEFSI_FP64 ? 8 : 4, h->np_tot, 8),
-          hx_lds_bytes(hp, nx, h->radius, 4, h->np_tot, 8));
-      check(lds_need <= kHxMaxLds, "too many projectors for the stencil pass (alpha row does not fit in LDS)");
-      const int64_t nkeys = (int64_t)hp.nty * nz;
-      auto key_of = [&](int64_t i) {
-        const int y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-        return (int64_t)(y / hp.ty) * nz + z;
-      };
-      std::vector<int> rptr(nkeys + 1, 0);
-      for (int64_t i = 0; i < nd; ++i) {
-        const int n = cnt[i + 1] - cnt[i];
-        if (n >= 1 && n <= 4) rptr[key_of(i) + 1] += 1;
-      }
-      for (int64_t k = 0; k < nkeys; ++k) rptr[k + 1] += rptr[k];
-      const int nrec = rptr[nkeys];
-      std::vector<HxRec<double>> r64(std::max(nrec, 1));
-      std::vector<HxRec<float>> r32(std::max(nrec, 1));
-      std::memset(r64.data(), 0, r64.size() * sizeof(HxRec<double>));
-      std::memset(r32.data(), 0, r32.size() * sizeof(HxRec<float>));
-      std::vector<int> rfill(rptr.begin(), rptr.end() - 1);
+      build_hx_records(h, h->hx_plan);
+      // points with more than four entries: one scatter record {point, first entry, entry
+      // count, 0} each, entries in atom order padded with zeros to a multiple of 4
       std::vector<int4> recs;
       std::vector<int> ecol;
       std::vector<double> evals;
       for (int64_t i = 0; i < nd; ++i) {
-        const int n = cnt[i + 1] - cnt[i];
-        if (n == 0) continue;
-        if (n <= 4) {
-          const int r = rfill[key_of(i)]++;
-          const int x = (int)(i % nx), y = (int)((i / nx) % ny);
-          int col[4] = {0, 0, 0, 0};
-          for (int k = 0; k < n; ++k) {
-            col[k] = eproj[cnt[i] + k];
-            r64[r].val[k] = eval[cnt[i] + k];
-            r32[r].val[k] = (float)eval[cnt[i] + k];
-          }
-          r64[r].lidx = r32[r].lidx = (y % hp.ty) * nx + x;
-          r64[r].c01 = r32[r].c01 = col[0] | (col[1] << 16);
-          r64[r].c23 = r32[r].c23 = col[2] | (col[3] << 16);
-          continue;
-        }
+        const int b = h->pt_cnt[i], n = h->pt_cnt[i + 1] - b;
+        if (n <= 4) continue;
         recs.push_back(make_int4((int)i, (int)ecol.size(), n, 0));
-        for (int k = cnt[i]; k < cnt[i + 1]; ++k) {
-          ecol.push_back(eproj[k]);
-          evals.push_back(eval[k]);
+        for (int k = b; k < b + n; ++k) {
+          ecol.push_back(h->pt_col[k]);
+          evals.push_back(h->pt_val[k]);
         }
         while (ecol.size() % 4) {
           ecol.push_back(0);
@@ -1197,12 +1238,6 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
         }
       }
       check(ecol.size() < ((size_t)1 << 31), "too many projector entries");
-      h->n_hxrec = nrec;
-      if (nrec > 0) {
-        h->hx_rec_ptr = upload(h, rptr.data(), rptr.size());
-        h->hx_rec64 = upload(h, r64.data(), r64.size());
-        h->hx_rec32 = upload(h, r32.data(), r32.size());
-      }
       h->n_pts = (int)recs.size();
       if (!recs.empty()) {
         h->rec = upload(h, recs.data(), recs.size());
@@ -1790,6 +1825,31 @@ int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void
       if (alpha_host) alpha_host[i] = 0.0;
       if (beta_host) beta_host[i] = 0.0;
     }
+  });
+}
+
+int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups) {
+  return guarded(h, [&] {
+    check(rows_per_thread >= 0 && rows_per_thread <= 4 && row_groups >= 0, "tiling parameters out of range");
+    check((rows_per_thread == 0) == (row_groups == 0), "give both tiling parameters, or neither");
+    const int eb = h->precision == CHEFSI_FP64 ? 8 : 4;
+    const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, eb, rows_per_thread, row_groups);
+    check(p.ok, "the requested stencil tiling does not fit this grid");
+    if (h->np_tot > 0)
+      build_hx_records(h, p);
+    else
+      h->hx_plan = p;
+  });
+}
+
+int chefsi_get_stencil_tiling(const chefsi_handle_t* hc, int32_t* tiling) {
+  chefsi_handle* h = const_cast<chefsi_handle*>(hc);
+  return guarded(h, [&] {
+    check(tiling != nullptr, "tiling is NULL");
+    tiling[0] = h->hx_plan.py;
+    tiling[1] = h->hx_plan.nyg;
+    tiling[2] = h->hx_plan.ty;
+    tiling[3] = h->hx_plan.kh;
   });
 }
 

@@ -75,7 +75,9 @@ struct HxPlan {
 };
 
 // Choose the tiling for one grid (deterministic in the shape only; ns only sets the z chunks).
-HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override);
+// py_override / nyg_override > 0 restrict the search to that rows-per-thread / row-group
+// count (the result's ok is false when the restricted tiling does not fit).
+HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override, int nyg_override);
 
 // Dynamic LDS of one stencil block; np_tot < 0: no projector records.
 size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes);

@@ -41,6 +41,7 @@ constexpr int kKS = 32;        // K per stage
 constexpr int kLd = kKS + 8;   // LDS row stride in bf16 (80 bytes: conflict-free 16-byte reads)
 constexpr int kRotJ = 128;     // rotation: output columns per block
 constexpr int kRotP = 256;     // rotation: grid points per block (64 per wave)
+constexpr int kSubStages = 512;  // projection: K stages summed in FP32 before an FP64 flush (16384 rows)
 
 __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -132,6 +133,24 @@ __device__ __forceinline__ void gram_store_lds(const GramStage& st, __bf16* ah, 
   }
 }
 
+// FP32 accumulators of a wave's 64 x 64 part into the FP64 partial tile (added to what the
+// same threads stored before when `add`), then cleared.  One writer per element, fixed order.
+__device__ __forceinline__ void flush_tile(f32x16 (&acc)[2][2], double* __restrict__ pt, int wm, int wn, int g,
+                                           int r32, bool add) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ii = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+        const int jj = wn * 64 + j * 32 + r32;
+        double* q = pt + ii * kT + jj;
+        *q = add ? *q + (double)acc[i][j][v] : (double)acc[i][j][v];
+        acc[i][j][v] = 0.f;
+      }
+}
+
 __global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float* __restrict__ A, const float* __restrict__ B,
                                                           int64_t nd, int ns, int nt, int ntiles, int64_t kchunk,
                                                           double* __restrict__ partial) {
@@ -165,6 +184,8 @@ __global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float* __restric
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
   const int nstage = (int)((ke - kb + kKS - 1) / kKS);
+  // partial tile, row-major 128 x 128: element (ii, jj) at ii * 128 + jj
+  double* pt = partial + ((int64_t)split * ntiles + tile) * (kT * kT);
   GramStage st;
   if (nstage > 0) {
     gram_load(st, pa, pb, kb + 16 * lhalf, ke, kb + kKS <= ke);
@@ -204,21 +225,14 @@ __global__ __launch_bounds__(256) void gram_bf16x3_kernel(const float* __restric
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
     }
     if (more) gram_store_lds(st, lds[buf ^ 1][0], lds[buf ^ 1][1], lds[buf ^ 1][2], lds[buf ^ 1][3], st_off);
+    // every kSubStages stages the FP32 sums move into the FP64 partial tile (FP32 sums span
+    // at most kSubStages * kKS rows of K)
+    if ((t + 1) % kSubStages == 0 && more) {
+      flush_tile(acc, pt, wm, wn, g, r32, t + 1 > kSubStages);
+    }
     __syncthreads();
   }
-
-  // partial tile, row-major 128 x 128: element (ii, jj) at ii * 128 + jj
-  double* pt = partial + ((int64_t)split * ntiles + tile) * (kT * kT);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int ii = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-        const int jj = wn * 64 + j * 32 + r32;
-        pt[ii * kT + jj] = (double)acc[i][j][v];
-      }
+  flush_tile(acc, pt, wm, wn, g, r32, nstage > kSubStages);
 }
 
 hipError_t launch_gram_bf16x3(const float* A, const float* B, int64_t nd, int ns, const GramPlan& p,

@@ -34,7 +34,6 @@
 #include "common.h"
 
 #include <algorithm>
-#include <cstdlib>
 
 namespace chefsi {
 
@@ -413,7 +412,7 @@ size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_
   return lds;
 }
 
-HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override) {
+HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int py_override, int nyg_override) {
   // Cost of a tiling, fitted to measured launches on 72^3 and 120^3 grids (FP64 and FP32):
   // idle lanes and rows beyond ny waste work, halo rows cost reads, blocks above 512
   // threads and two rows per thread cost occupancy (more so in FP32 for the former and in
@@ -422,8 +421,6 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   HxPlan best;
   double best_cost = 1e300;
   bool best_tall = false;
-  int nyg_override = 0;
-  if (const char* e = std::getenv("CHEFSI_HX_NYG")) nyg_override = std::atoi(e);  // tiling experiments only
   const double big_block = elem_bytes == 8 ? 1.2 : 1.35;
   const double two_rows = elem_bytes == 8 ? 1.3 : 1.2;
   const int pys[] = {1, 2, 3, 4};

@@ -1,0 +1,49 @@
+"""Write the FP64 oracle's Ritz values for the reduced slab workload (30 x 30 x 90 grid,
+Dirichlet z, 25 atoms x 4 projectors, Ns 300, degree 24) after 1..6 CheFSI iterations
+(Algorithm 1, scaled Chebyshev filter, bounds updated between iterations) from the
+seeded X0, to tests/golden/cfg3_twin_ritz.txt.
+
+Only the oracle and the seeded input generator are used; the GPU tests compare the
+library's whole solves with these values.  Takes about 15 minutes on 8 host cores.
+
+    python tests/golden/make_cfg3_twin_ritz.py
+"""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import chefsi as oc  # noqa: E402
+from paper_2302_09708_amd import inputs  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfg3_twin_ritz.txt")
+
+
+def main():
+    cfg = inputs.CONFIGS["cfg3_twin"]
+    prob = inputs.make_problem(cfg)
+    x0 = inputs.initial_block(prob.nd, cfg.ns, cfg.x_seed).T
+    lo, cut, hi = oc.spectral_bounds(prob)
+    rows = []
+
+    def record(it, d, x, lam_lo, lam_cut):
+        rows.append(np.array(d))
+        print(f"iteration {it + 1}: D_1 = {d[0]:.12f}", flush=True)
+
+    oc.chefsi(prob, x0, cfg.degree, cfg.n_iter, lo, cut, hi, callback=record)
+    with open(OUT, "w") as f:
+        f.write("# FP64 oracle Ritz values (Ha) of the reduced slab workload cfg3_twin\n")
+        f.write(f"# grid {cfg.n} h {cfg.h} bc {cfg.bc}, {cfg.n_atoms} atoms x {cfg.nproj_per_atom} projectors, "
+                f"Ns {cfg.ns}, degree {cfg.degree}, X0 seed {cfg.x_seed}\n")
+        f.write(f"# bounds of the first step lam_lo lam_cut lam_hi: {oc.spectral_bounds(prob)}\n")
+        f.write("# row k = Ritz values after k+1 iterations (Algorithm 1), ascending\n")
+        f.write("# written by tests/golden/make_cfg3_twin_ritz.py (oracle only)\n")
+        for d in rows:
+            f.write(" ".join(f"{v:.15e}" for v in d) + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,109 @@
+"""Every stencil-pass tiling against the FP64 oracle (Sec. 2.1 stencil + Veff + projectors).
+
+The planner picks rows per thread (PY) and halo values per thread (KH) from the grid
+shape; the largest workloads run variants (two rows per thread, four halo values) that
+small default grids never select.  chefsi_set_stencil_tiling forces each variant on a
+grid small enough for the oracle, for both element types, for H X alone, for the
+refinement's FP64 product of an FP32 block, and for a whole mixed solve.  Results must
+not depend on the tiling (every point sums its terms in the same order), so the variants
+are also compared bit for bit with each other.
+"""
+import numpy as np
+import pytest
+
+from oracle import chefsi as oc
+from oracle.hamiltonian import apply_h
+from paper_2302_09708_amd import inputs
+from tests._gpu import dev, host, stencil_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (rows per thread, row groups): with nx = 40 and r = 6 these give KH = 2 and KH = 4 for
+# both PY = 1 and PY = 2 (KH = 4 when 2 r nx > 2 x the block's lanes)
+TILINGS = [(1, 3), (1, 8), (1, 24), (2, 4), (2, 6), (2, 12), (3, 3), (4, 2)]
+GRIDS = [((40, 24, 16), (0, 0, 0)), ((40, 23, 18), (0, 1, 1))]
+
+
+@pytest.fixture(scope="module")
+def cs():
+    from paper_2302_09708_amd import chefsi
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    chefsi.load()
+    return chefsi
+
+
+@pytest.mark.parametrize("grid", GRIDS, ids=[f"{g[0]}{g[1]}" for g in GRIDS])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_h_every_tiling(cs, grid, prec):
+    n, bc = grid
+    prob = inputs.small_problem(n=n, h=(0.3, 0.27, 0.33), bc=bc, fd_order=12, n_atoms=6, nproj_per_atom=4,
+                                seed=sum(n))
+    ns = 5
+    dt = "float64" if prec == "fp64" else "float32"
+    X = np.random.default_rng(7).standard_normal((prob.nd, ns)).astype(dt)
+    ref = apply_h(prob, X.astype(np.float64))
+    scale = stencil_scale(prob) * np.abs(X).max()
+    tol = 1e-12 * scale if prec == "fp64" else 2e-6 * scale
+    h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+    default = h.chefsi_get_stencil_tiling()
+    seen, outs = set(), []
+    for py, nyg in TILINGS:
+        try:
+            h.chefsi_set_stencil_tiling(py, nyg)
+        except cs.ChefsiError as e:
+            assert e.status == cs.ERR_INVALID_ARG
+            continue
+        t = h.chefsi_get_stencil_tiling()
+        assert t[0] == py and t[1] == nyg and t[2] == py * nyg
+        print(f"{prec} {n}{bc}: tiling PY={t[0]} groups={t[1]} rows={t[2]} KH={t[3]}", flush=True)
+        Yd = torch.zeros(ns, prob.nd, dtype=getattr(torch, dt), device="cuda")
+        h.chefsi_apply_h(dev(X, dt), Yd, ns, ws)
+        torch.cuda.synchronize()
+        got = host(Yd)
+        assert np.abs(got - ref).max() <= tol
+        seen.add((t[0], t[3]))
+        outs.append(got)
+    assert {(1, 2), (1, 4), (2, 2), (2, 4)} <= seen
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    h.chefsi_set_stencil_tiling(0, 0)
+    assert h.chefsi_get_stencil_tiling() == default
+
+
+@pytest.mark.parametrize("tiling", [(1, 3), (2, 4), (2, 12)])
+def test_refine_degree0_every_tiling(cs, tiling):
+    """The refinement's H X in FP64 from an FP32 block (the <float, double, double> pass)."""
+    prob = inputs.small_problem(n=(40, 24, 16), bc=(0, 0, 1), n_atoms=5, nproj_per_atom=4, seed=13)
+    ns = 12
+    X = np.random.default_rng(2).standard_normal((prob.nd, ns)).astype(np.float32).astype(np.float64)
+    hs, ms = oc.project(prob, X)
+    d_ref, _ = oc.diagonalize(hs, ms)
+    h = cs.Handle(prob, precision=cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+    h.chefsi_set_stencil_tiling(*tiling)
+    d = h.chefsi_refine_fp64(dev(X, "float32"), ns, ws, 0)
+    assert np.abs(d - d_ref).max() <= 1e-10 * np.abs(d_ref).max()
+
+
+def test_mixed_solve_with_two_rows_and_four_halo_values(cs):
+    """A whole mixed solve (mixed steps + FP64 refinement) in the tiling the 120^3 FP32
+    workload runs (two rows per thread, four halo values per thread) against the oracle."""
+    prob = inputs.small_problem(n=(40, 24, 16), bc=(0, 0, 1), n_atoms=5, nproj_per_atom=4, seed=13)
+    ns, degree, n_iter = 24, 12, 5
+    x0 = inputs.initial_block(prob.nd, ns, 77).T
+    lo, cut, hi = oc.spectral_bounds(prob)
+    d_ref, x_ref = oc.chefsi(prob, x0, degree, n_iter, lo, cut, hi)
+    h = cs.Handle(prob, precision=cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+    h.chefsi_set_stencil_tiling(2, 4)
+    assert h.chefsi_get_stencil_tiling()[3] == 4
+    Xd = dev(x0, "float32")
+    d, _, _ = h.solve(Xd, ns, degree, n_iter, ws, bounds=(lo, cut, hi))
+    k = oc.gap_index(d_ref, int(ns / 1.2))
+    err = np.abs(d[:k] - d_ref[:k]).max()
+    rho = oc.subspace_residual(x_ref, host(Xd), k)
+    print(f"PY=2 KH=4 mixed solve: N_chk={k} max|dRitz|={err:.2e} rho={rho:.2e}", flush=True)
+    assert err <= 1e-5 and rho <= 1e-5
