@@ -143,8 +143,8 @@ int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
  * for one row per thread, 512 otherwise).  chefsi_set_stencil_tiling(h, 0, 0) restores the
  * library's choice; another pair replaces it (the projector records are rebuilt) and
  * returns CHEFSI_ERR_INVALID_ARG, keeping the current tiling, when it does not fit the
- * grid (rows_per_thread 1..4).  Results do not depend on the tiling: every point sums its
- * stencil, potential and projector terms in the same order.  For tuning and tests.
+ * grid (rows_per_thread 1..4).  Results agree across tilings to rounding (each point
+ * sums the same terms; the last bits can differ).  For tuning and tests.
  * chefsi_get_stencil_tiling writes {rows_per_thread, row_groups, tile rows, halo values
  * per thread} to tiling[0..3]. */
 int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups);
@@ -205,6 +205,26 @@ int chefsi_nonlocal_forces(chefsi_handle_t* h, const void* X, int32_t ns, const 
  * stream is synchronised.  Fixed-order sums (bitwise reproducible).  Errors as above. */
 int chefsi_kinetic_stress(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host, void* ws,
                           size_t ws_bytes, void* stream, double* stress_host);
+
+/* Nonlocal (Kleinman-Bylander) component of the stress, the other quantity Sec. 2 computes
+ * with the gradient of the orbitals followed by the nonlocal projectors.  Under a
+ * homogeneous strain the projectors are sampled at the strained displacement from their
+ * atom; the strain derivative of E_nl = sum_n g_n sum_{J,a} gamma_Ja (dV chi_Ja^T psi_n)^2,
+ * integrated by parts over each support, is
+ *   sigma_ab = -(1 / Omega) [delta_ab E_nl + 2 sum_n g_n sum_{J,a} gamma_Ja alpha beta_ab],
+ *   alpha = dV chi_Ja^T psi_n,  beta_ab = dV sum_i chi_Ja(i) d_b(i) (d psi_n / dx_a)(i),
+ * d/dx_a the handle's central FD first derivative, Omega = Nd dV (Ha / bohr^3).
+ * disp_host: HOST, 3 doubles per support point in the order of chefsi_nonlocal_t.supp_idx
+ * (atom by atom), the displacement d = r_i - R_J of the point from its atom (the minimum
+ * image the projector values were evaluated at); may be NULL when the handle has no
+ * projectors.  X, occ_host, ws (chefsi_forces_workspace_bytes) as chefsi_nonlocal_forces;
+ * stress_host: 9 doubles, row-major (a, b), written after the stream is synchronised.  Not
+ * symmetric in general: it is when the projector set of every atom is closed under
+ * rotations (e.g. equal energies within an l shell).  FP64 arithmetic; fixed-order sums.
+ * Errors: ERR_INVALID_ARG (NULL pointers, non-finite occupations or displacements),
+ * ERR_WORKSPACE, ERR_HIP. */
+int chefsi_nonlocal_stress(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host,
+                           const double* disp_host, void* ws, size_t ws_bytes, void* stream, double* stress_host);
 
 /* Y = H X for an Nd x ns block (Sec. 2.1: stencil + Veff + nonlocal).  X and Y
  * are distinct device blocks of the handle's element type. */

@@ -43,7 +43,7 @@ EXPORTS = (
     "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
     "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
     "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
-    "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling",
+    "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling", "chefsi_nonlocal_stress",
 )
 
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.chefsi_forces_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_nonlocal_forces.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
     lib.chefsi_kinetic_stress.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
+    lib.chefsi_nonlocal_stress.argtypes = [vp, vp, i32, pd, pd, vp, sz, vp, pd]
     lib.chefsi_lanczos_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_lanczos_bound.argtypes = [vp, vp, i32, vp, sz, vp, pd, pd, pd, pd]
     lib.chefsi_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp]
@@ -347,6 +348,20 @@ class Handle:
         self._check(self._lib.chefsi_kinetic_stress(self.h, _ptr(X), int(ns), g.ctypes.data_as(C.POINTER(C.c_double)),
                                                     _ptr(ws), self._wsb(ws, ws_bytes), _stream(stream),
                                                     out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(3, 3)
+
+    def chefsi_nonlocal_stress(self, X, ns, occ, disp, ws, ws_bytes=None, stream=None) -> np.ndarray:
+        """3 x 3 nonlocal stress of the ns orbitals X with occupations occ; disp holds the
+        (n_support, 3) displacements of the support points from their atoms."""
+        g = np.ascontiguousarray(occ, dtype=np.float64).reshape(-1)
+        if g.size != int(ns):
+            raise ValueError("need one occupation per orbital")
+        d = np.ascontiguousarray(disp, dtype=np.float64).reshape(-1)
+        out = np.zeros(9)
+        self._check(self._lib.chefsi_nonlocal_stress(self.h, _ptr(X), int(ns), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                                     d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(ws),
+                                                     self._wsb(ws, ws_bytes), _stream(stream),
+                                                     out.ctypes.data_as(C.POINTER(C.c_double))))
         return out.reshape(3, 3)
 
     def chefsi_lanczos_workspace_bytes(self) -> int:

@@ -1614,7 +1614,8 @@ void lanczos_impl(chefsi_handle* h, const TV* v0, int steps, void* ws, const LzL
 // blocks (np_tot x ns FP64), dV per projector column, occupations, forces.
 // ---------------------------------------------------------------------------
 struct FoLayout {
-  size_t grad = 0, alpha = 0, beta = 0, dvc = 0, occ = 0, forces = 0, spart = 0, total = 0;
+  size_t grad = 0, alpha = 0, beta = 0, dvc = 0, occ = 0, forces = 0, spart = 0, disp = 0, chiw = 0, nlsum = 0,
+         total = 0;
 };
 
 FoLayout forces_layout(const chefsi_handle* h, int ns) {
@@ -1635,6 +1636,16 @@ FoLayout forces_layout(const chefsi_handle* h, int ns) {
   off += align256((size_t)std::max(1, h->n_atoms) * 3 * 8);
   L.spart = off;  // stress block sums (kVecBlocks x 6) and the six totals
   off += align256(((size_t)kVecBlocks * 6 + 8) * 8);
+  // nonlocal stress: support-point displacements, the three displacement-weighted copies of
+  // the projector values, and per-atom sums (energy + one n_atoms x 3 block per gradient
+  // direction)
+  const size_t nsupp = h->supp_idx_h.size(), nchi = h->chi_h.size();
+  L.disp = off;
+  off += align256(std::max<size_t>(1, 3 * nsupp) * 8);
+  L.chiw = off;
+  off += align256(std::max<size_t>(1, 3 * nchi) * 8);
+  L.nlsum = off;
+  off += align256((size_t)std::max(1, h->n_atoms) * 12 * 8);
   L.total = off;
   return L;
 }
@@ -1704,6 +1715,95 @@ void forces_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, 
   HIP_TRY(e);
 }
 
+// Nonlocal stress (see chefsi.h): alpha = dV chi^T psi, then per gradient direction a the
+// gathers beta_ab = dV (chi d_b)^T (d psi / dx_a) and the per-atom sums
+// -2 sum_k gamma_k sum_v g_v alpha beta_ab (force_kernel), and the energy's per-atom sums
+// from beta = alpha; the atom sums are added on the host in atom order.
+template <typename TV>
+void nonlocal_stress_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, const double* disp_host,
+                          void* ws, const FoLayout& L, hipStream_t s, double* stress_host) {
+  const int na = h->n_atoms;
+  const size_t nsupp = h->supp_idx_h.size(), nchi = h->chi_h.size();
+  const std::vector<double> dvc(std::max(1, h->np_tot), h->dv);
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.dvc), dvc.data(), dvc.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.occ), occ_host, (size_t)ns * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<double>(ws, L.disp), disp_host, 3 * nsupp * 8, hipMemcpyHostToDevice, s));
+  double* chiw = at<double>(ws, L.chiw);
+  ChiDispArgs cd{};
+  cd.chi = h->chi64;
+  cd.disp = at<double>(ws, L.disp);
+  cd.supp_off = h->supp_off;
+  cd.chi_off = h->chi_off;
+  cd.nproj = h->nproj;
+  cd.n_atoms = na;
+  cd.nchi = (int64_t)nchi;
+  cd.out = chiw;
+  HIP_TRY(launch_chi_disp(cd, s));
+  double* alpha = at<double>(ws, L.alpha);
+  double* beta = at<double>(ws, L.beta);
+  double* grad = at<double>(ws, L.grad);
+  double* sums = at<double>(ws, L.nlsum);  // [0]: energy, [1 + a]: direction a; n_atoms x 3 each
+  const double* dv = at<double>(ws, L.dvc);
+  HIP_TRY((launch_nl_project<TV, double>(nl_args<TV, double>(h, X, ns, h->chi64, dv, alpha), s)));
+  ForceArgs f{};
+  f.alpha = alpha;
+  f.occ = at<double>(ws, L.occ);
+  f.gdv = h->gdv64;
+  f.nproj = h->nproj;
+  f.poff = h->poff;
+  f.dv = h->dv;
+  f.n_atoms = na;
+  f.np_tot = h->np_tot;
+  f.ns = ns;
+  f.beta = alpha;
+  f.dir = 0;
+  f.forces = sums;
+  HIP_TRY(launch_forces(f, s));
+  const std::vector<double> c = first_derivative_weights(h->radius);
+  for (int a = 0; a < 3; ++a) {
+    GradArgs<TV> g{};
+    g.x = X;
+    g.out = grad;
+    g.nd = h->nd;
+    g.nx = h->n[0];
+    g.ny = h->n[1];
+    g.nz = h->n[2];
+    g.dir = a;
+    g.r = h->radius;
+    g.periodic = h->bc[a] == 0 ? 1 : 0;
+    for (int p = 0; p <= h->radius; ++p) g.c[p] = c[p];
+    g.inv_h = 1.0 / h->h[a];
+    HIP_TRY(launch_grad<TV>(g, ns, s));
+    for (int b = 0; b < 3; ++b) {
+      HIP_TRY((launch_nl_project<double, double>(
+          nl_args<double, double>(h, grad, ns, chiw + (size_t)b * nchi, dv, beta), s)));
+      f.beta = beta;
+      f.dir = b;
+      f.forces = sums + (size_t)(1 + a) * na * 3;
+      HIP_TRY(launch_forces(f, s));
+    }
+  }
+  const size_t nb = (size_t)na * 12 * 8;
+  double* pin = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&pin, nb, hipHostMallocDefault));
+  hipError_t e = hipMemcpyAsync(pin, sums, nb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  std::vector<double> hs;
+  if (e == hipSuccess) hs.assign(pin, pin + (size_t)na * 12);
+  (void)hipHostFree(pin);
+  HIP_TRY(e);
+  // energy: force_kernel gave -2 sum gamma g alpha^2 per atom (component 0)
+  double e_nl = 0.0;
+  for (int J = 0; J < na; ++J) e_nl += -0.5 * hs[(size_t)J * 3];
+  const double omega = (double)h->nd * h->dv;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double t = 0.0;  // -2 sum g gamma alpha beta_ab
+      for (int J = 0; J < na; ++J) t += hs[(size_t)(1 + a) * na * 3 + (size_t)J * 3 + b];
+      stress_host[a * 3 + b] = -((a == b ? e_nl : 0.0) - t) / omega;
+    }
+}
+
 template <typename TV>
 void kinetic_stress_impl(chefsi_handle* h, const TV* X, int ns, const double* occ_host, void* ws, const FoLayout& L,
                          hipStream_t s, double* stress_host) {
@@ -1758,6 +1858,30 @@ int chefsi_kinetic_stress(chefsi_handle_t* h, const void* X, int32_t ns, const d
       kinetic_stress_impl<double>(h, (const double*)X, ns, occ_host, ws, L, s, stress_host);
     else
       kinetic_stress_impl<float>(h, (const float*)X, ns, occ_host, ws, L, s, stress_host);
+  });
+}
+
+int chefsi_nonlocal_stress(chefsi_handle_t* h, const void* X, int32_t ns, const double* occ_host,
+                           const double* disp_host, void* ws, size_t ws_bytes, void* stream, double* stress_host) {
+  return guarded(h, [&] {
+    check(X != nullptr && occ_host != nullptr && stress_host != nullptr, "X, occ and stress must not be NULL");
+    check_ns(h, ns);
+    for (int i = 0; i < ns; ++i) check(std::isfinite(occ_host[i]), "occupations must be finite");
+    if (h->n_atoms == 0 || h->np_tot == 0) {
+      std::fill(stress_host, stress_host + 9, 0.0);
+      return;
+    }
+    check(disp_host != nullptr, "disp must not be NULL when there are projectors");
+    const size_t nsupp = h->supp_idx_h.size();
+    for (size_t i = 0; i < 3 * nsupp; ++i) check(std::isfinite(disp_host[i]), "displacements must be finite");
+    check(ws != nullptr, "ws is NULL");
+    const FoLayout L = forces_layout(h, ns);
+    if (ws_bytes < L.total) throw Error{CHEFSI_ERR_WORKSPACE, "workspace smaller than chefsi_forces_workspace_bytes"};
+    hipStream_t s = (hipStream_t)stream;
+    if (h->precision == CHEFSI_FP64)
+      nonlocal_stress_impl<double>(h, (const double*)X, ns, occ_host, disp_host, ws, L, s, stress_host);
+    else
+      nonlocal_stress_impl<float>(h, (const float*)X, ns, occ_host, disp_host, ws, L, s, stress_host);
   });
 }
 

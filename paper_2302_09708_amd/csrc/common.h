@@ -235,6 +235,19 @@ struct StressArgs {
 
 template <typename TV>
 hipError_t launch_stress_sums(const StressArgs<TV>& a, hipStream_t s);
+// Nonlocal stress weights: out[b * nchi + e] = chi[e] * disp[3 s + b] (b = 0..2) for every
+// projector value e (atom-major, the layout of chi) at its support point s.
+struct ChiDispArgs {
+  const double* chi;
+  const double* disp;     // 3 per support point, support-point order of supp_idx
+  const int* supp_off;    // n_atoms + 1
+  const int64_t* chi_off; // n_atoms
+  const int* nproj;       // n_atoms
+  int n_atoms;
+  int64_t nchi;
+  double* out;            // 3 * nchi
+};
+hipError_t launch_chi_disp(const ChiDispArgs& a, hipStream_t s);
 hipError_t launch_forces(const ForceArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -126,7 +126,29 @@ __global__ __launch_bounds__(64) void stress_sum_kernel(const double* __restrict
   out[threadIdx.x] = s;
 }
 
+// out[b * nchi + e] = chi[e] * disp[3 s + b], b = 0, 1, 2, for every projector value e of
+// atom J (block J) at its support point s: the projectors weighted by the components of the
+// displacement of the point from the atom, for the nonlocal stress's strain derivative.
+__global__ __launch_bounds__(256) void chi_disp_kernel(ChiDispArgs a) {
+  const int J = blockIdx.x;
+  const int s0 = a.supp_off[J], nj = a.supp_off[J + 1] - s0;
+  const int64_t c0 = a.chi_off[J];
+  const int nv = nj * a.nproj[J];
+  for (int e = threadIdx.x; e < nv; e += 256) {
+    const int s = e % nj;
+    const double v = a.chi[c0 + e];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) a.out[(int64_t)b * a.nchi + c0 + e] = v * a.disp[3 * (int64_t)(s0 + s) + b];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_chi_disp(const ChiDispArgs& a, hipStream_t s) {
+  if (a.n_atoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chi_disp_kernel, dim3((unsigned)a.n_atoms), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 template <typename TV>
 hipError_t launch_stress_sums(const StressArgs<TV>& a, hipStream_t s) {

@@ -38,7 +38,7 @@ def main():
         f.write("# FP64 oracle Ritz values (Ha) of the reduced slab workload cfg3_twin\n")
         f.write(f"# grid {cfg.n} h {cfg.h} bc {cfg.bc}, {cfg.n_atoms} atoms x {cfg.nproj_per_atom} projectors, "
                 f"Ns {cfg.ns}, degree {cfg.degree}, X0 seed {cfg.x_seed}\n")
-        f.write(f"# bounds of the first step lam_lo lam_cut lam_hi: {oc.spectral_bounds(prob)}\n")
+        f.write("# bounds of the first step lam_lo lam_cut lam_hi: %.15e %.15e %.15e\n" % tuple(map(float, oc.spectral_bounds(prob))))
         f.write("# row k = Ritz values after k+1 iterations (Algorithm 1), ascending\n")
         f.write("# written by tests/golden/make_cfg3_twin_ritz.py (oracle only)\n")
         for d in rows:

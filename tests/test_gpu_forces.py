@@ -109,3 +109,56 @@ def test_kinetic_stress_matches_oracle(cs, case):
         xr = X if precision == cs.FP64 else X.astype(np.float32).astype(np.float64)
         r = ref if precision == cs.FP64 else kinetic_stress(prob, xr, occ)
         assert np.abs(got - r).max() <= tol * np.abs(r).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_nonlocal_stress_matches_oracle(cs, case):
+    """Nonlocal stress through the C-ABI against the oracle's (pinned to the strain
+    derivative of the nonlocal energy): FP64 to 1e-11 of the largest component, mixed
+    handles (FP32 orbitals, FP64 arithmetic) to 1e-9 of the FP32-rounded orbitals' stress;
+    bitwise reproducible and additive over orbital chunks.  The p energies are made
+    unequal in one case so the stress is not symmetric."""
+    from oracle.forces import nonlocal_stress
+    prob = _problem(case)
+    if case[0] == "slab":
+        prob.gamma = prob.gamma * np.tile([1.0, 0.6, 1.3, 0.9], prob.n_atoms)
+    ns = case[2]
+    X = inputs.initial_block(prob.nd, ns, 3003).T
+    occ = np.linspace(2.0, 0.3, ns)
+    disp = inputs.support_displacements(prob)
+    for precision, tol in ((cs.FP64, 1e-11), (cs.MIXED, 1e-9)):
+        xr = X if precision == cs.FP64 else X.astype(np.float32).astype(np.float64)
+        ref = nonlocal_stress(prob, xr, occ, disp)
+        h = cs.Handle(prob, precision=precision, max_ns=ns)
+        ws = torch.empty(h.chefsi_forces_workspace_bytes(ns), dtype=torch.uint8, device="cuda")
+        dt = torch.float64 if precision == cs.FP64 else torch.float32
+        Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(device="cuda", dtype=dt)
+        got = h.chefsi_nonlocal_stress(Xd, ns, occ, disp, ws)
+        again = h.chefsi_nonlocal_stress(Xd, ns, occ, disp, ws)
+        half = ns // 2
+        parts = (h.chefsi_nonlocal_stress(Xd[:half], half, occ[:half], disp, ws) +
+                 h.chefsi_nonlocal_stress(Xd[half:], ns - half, occ[half:], disp, ws))
+        h.close()
+        print(f"nonlocal stress {case[0]} prec={precision}: max|err| / max|sigma| = "
+              f"{np.abs(got - ref).max() / np.abs(ref).max():.2e}", flush=True)
+        assert np.array_equal(got, again)
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+        assert np.abs(parts - got).max() <= 1e-12 * np.abs(ref).max()
+        if case[0] == "slab":
+            assert np.abs(ref - ref.T).max() >= 1e-3 * np.abs(ref).max()
+
+
+def test_nonlocal_stress_errors(cs):
+    prob = _problem(CASES[2])
+    h = cs.Handle(prob, precision=cs.FP64, max_ns=4)
+    ws = torch.empty(h.chefsi_forces_workspace_bytes(4), dtype=torch.uint8, device="cuda")
+    Xd = torch.zeros(4, prob.nd, dtype=torch.float64, device="cuda")
+    disp = inputs.support_displacements(prob)
+    bad = disp.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(cs.ChefsiError):
+        h.chefsi_nonlocal_stress(Xd, 4, np.ones(4), bad, ws)
+    with pytest.raises(cs.ChefsiError):
+        h.chefsi_nonlocal_stress(Xd, 4, np.ones(4), disp, ws, ws_bytes=256)
+    assert np.array_equal(h.chefsi_nonlocal_stress(Xd, 4, np.ones(4), disp, ws), np.zeros((3, 3)))
+    h.close()

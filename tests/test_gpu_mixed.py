@@ -232,3 +232,55 @@ def test_mixed_falls_back_to_fp64_on_ill_conditioned_blocks(cs, k):
           f"max|dRitz| vs FP64 = {err:.2e}", flush=True)
     assert out[cs.MIXED][1] >= 1
     assert err <= 1e-5
+
+
+def _golden_twin():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_twin_ritz.txt")
+    rows, bounds = [], None
+    for line in open(path):
+        if line.startswith("# bounds of the first step"):
+            bounds = tuple(float(v) for v in line.split(":")[1].split())
+        elif not line.startswith("#") and line.strip():
+            rows.append(np.array([float(v) for v in line.split()]))
+    return bounds, rows
+
+
+def test_cfg3_twin_solves_against_stored_oracle_ritz_values(cs):
+    """The reduced slab workload (30 x 30 x 90, Dirichlet z, 25 atoms, Ns 300, degree 24,
+    6 filter passes): FP64 solve against the oracle's Ritz values (stored by
+    tests/golden/make_cfg3_twin_ritz.py, which runs only the oracle: its 6 iterations take
+    ~15 minutes on the host) to 1e-10 Ha; mixed solve (5 mixed steps + FP64 refinement) to
+    1e-5 Ha on the gap-bounded leading block.  The mixed subspace is compared with the FP64
+    solve's (rho <= 1e-5), whose subspace the oracle pins on the smaller workloads and whose
+    Ritz values it pins here; the mixed block's residuals are checked with the oracle's H."""
+    from oracle.hamiltonian import apply_h
+    cfg = inputs.CONFIGS["cfg3_twin"]
+    prob = inputs.make_problem(cfg)
+    bounds, rows = _golden_twin()
+    d_ref = rows[cfg.n_iter - 1]
+    lo, cut, hi = oc.spectral_bounds(prob)
+    assert np.allclose((lo, cut, hi), bounds, rtol=1e-14, atol=0)
+    x0 = inputs.initial_block(prob.nd, cfg.ns, cfg.x_seed)
+    k = oc.gap_index(d_ref, int(cfg.ns / 1.2))
+    out = {}
+    for prec, dt in ((cs.FP64, "float64"), (cs.MIXED, "float32")):
+        h, ws = _handle(cs, prob, cfg.ns, prec)
+        Xd = torch.from_numpy(x0).to(device="cuda", dtype=getattr(torch, dt))
+        d, _, _ = h.solve(Xd, cfg.ns, cfg.degree, cfg.n_iter, ws, bounds=(lo, cut, hi))
+        out[prec] = (d, host(Xd))
+        h.close()
+    d64, x64 = out[cs.FP64]
+    dmx, xmx = out[cs.MIXED]
+    err64 = np.abs(d64 - d_ref).max()
+    errmx = np.abs(dmx[:k] - d_ref[:k]).max()
+    rho = oc.subspace_residual(x64, xmx, k)
+    res = oc.residual_norms(prob, xmx[:, :k], dmx[:k])
+    res64 = oc.residual_norms(prob, x64[:, :k], d64[:k])
+    print(f"cfg3 twin: N_chk={k} FP64 max|dRitz|={err64:.2e} mixed max|dRitz|={errmx:.2e} rho(mixed, FP64)={rho:.2e} "
+          f"max residual mixed {res.max():.2e} FP64 {res64.max():.2e}", flush=True)
+    assert err64 <= 1e-10
+    assert errmx <= 1e-5
+    assert rho <= 1e-5
+    assert np.abs(xmx.T @ xmx - np.eye(cfg.ns)).max() <= 1e-5
+    assert res.max() <= res64.max() + 1e-4 * max(abs(lo), abs(hi))
