@@ -231,6 +231,27 @@ int chefsi_nonlocal_stress(chefsi_handle_t* h, const void* X, int32_t ns, const 
 int chefsi_apply_h(chefsi_handle_t* h, const void* X, void* Y, int32_t ns,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the library's static device scratch (64 MiB per GPU, held from the first
+ * chefsi_create on that GPU until the process ends). */
+#define CHEFSI_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it): Y = H X
+ * exactly as chefsi_apply_h computes it (same kernels, same bits), with the
+ * projector coefficients alpha (np_tot x ns values of the handle's element type) in
+ * the library's static per-GPU scratch instead of a caller workspace.  The call
+ * allocates nothing (no hipMalloc/hipFree, no allocating library routine, no event
+ * creation) and only enqueues kernels on `stream`.  X and Y are distinct caller-owned
+ * device blocks (Nd x ns, ld Nd, the handle's element type).
+ * Limit: np_tot * ns * sizeof(element) <= CHEFSI_STATIC_SCRATCH_BYTES (query it with
+ * chefsi_static_scratch_bytes); larger requests return CHEFSI_ERR_WORKSPACE before any
+ * launch (call on fewer orbitals at a time).  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (other streams, other threads, other
+ * handles) race and must be serialised by the caller.  The scratch is fully written
+ * before it is read in each call; nothing carries over from the previous call. */
+int chefsi_static_scratch_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes);
+int chefsi_apply_h_static(chefsi_handle_t* h, const void* X, void* Y, int32_t ns, void* stream);
+
 /* X <- scaled Chebyshev filter of degree m >= 1 applied to X, in place
  * (Alg. 1, Filtering).  Requires lam_lo < lam_cut < lam_hi. */
 int chefsi_filter(chefsi_handle_t* h, void* X, int32_t ns, int32_t degree,

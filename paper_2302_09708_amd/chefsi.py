@@ -31,6 +31,8 @@ ERR_NONFINITE = 6
 ERR_SOLVER = 7
 ERR_OOM = 8
 
+STATIC_SCRATCH_BYTES = 64 << 20  # CHEFSI_STATIC_SCRATCH_BYTES
+
 PROF_HX, PROF_NL, PROF_GRAM, PROF_REDUCE, PROF_ROT, PROF_EIG, PROF_COPY, PROF_FALLBACK = range(8)
 
 # every symbol include/chefsi.h declares
@@ -44,6 +46,7 @@ EXPORTS = (
     "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
     "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
     "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling", "chefsi_nonlocal_stress",
+    "chefsi_static_scratch_bytes", "chefsi_apply_h_static",
 )
 
 
@@ -91,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.chefsi_get_stencil_tiling.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
+    lib.chefsi_static_scratch_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    lib.chefsi_apply_h_static.argtypes = [vp, vp, vp, i32, vp]
     lib.chefsi_update_veff.argtypes = [vp, pd, vp]
     lib.chefsi_forces_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_nonlocal_forces.argtypes = [vp, vp, i32, pd, vp, sz, vp, pd]
@@ -382,6 +387,14 @@ class Handle:
     def chefsi_apply_h(self, X, Y, ns, ws, ws_bytes=None, stream=None):
         self._check(self._lib.chefsi_apply_h(self.h, _ptr(X), _ptr(Y), int(ns), _ptr(ws),
                                              self._wsb(ws, ws_bytes), _stream(stream)))
+
+    def chefsi_static_scratch_bytes(self, ns):
+        b = C.c_size_t()
+        self._check(self._lib.chefsi_static_scratch_bytes(self.h, int(ns), C.byref(b)))
+        return b.value
+
+    def chefsi_apply_h_static(self, X, Y, ns, stream=None):
+        self._check(self._lib.chefsi_apply_h_static(self.h, _ptr(X), _ptr(Y), int(ns), _stream(stream)))
 
     def chefsi_filter(self, X, ns, degree, lam_lo, lam_cut, lam_hi, ws, ws_bytes=None, stream=None):
         self._check(self._lib.chefsi_filter(self.h, _ptr(X), int(ns), int(degree), float(lam_lo), float(lam_cut),

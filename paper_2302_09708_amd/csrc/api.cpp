@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -80,6 +81,35 @@ struct EventPair {
 };
 
 }  // namespace
+
+// Scratch of chefsi_apply_h_static: the projector coefficients alpha (np_tot x ns of the
+// handle's compute type) live in this file-scope device array instead of a caller
+// workspace.  Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device memory: its device
+// address is looked up once per device (hipGetSymbolAddress, that device current) and
+// only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CHEFSI_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices] = {};
+
+// device address of `scratch` on the current device (looked up on first use per device)
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) throw Error{CHEFSI_ERR_HIP, "device ordinal out of range"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      throw Error{CHEFSI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
 
 struct chefsi_handle {
   int device = 0;
@@ -1163,6 +1193,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     }
 
     HIP_TRY(hipGetDevice(&h->device));
+    (void)scratch_address(h->device);  // the static scratch's device address, once per device
     BLAS_TRY(rocblas_create_handle(&h->blas));
     // the dense stage must give the same bits whatever else runs on the device (results of
     // a request alone and among others are compared bit for bit): no atomics in rocBLAS
@@ -1325,6 +1356,42 @@ int chefsi_spectral_bounds(const chefsi_handle_t* hc, double* lam_lo, double* la
     if (lam_hi) *lam_hi = hi;
     if (lam_lo) *lam_lo = lo;
     if (lam_cut) *lam_cut = lo + 0.1 * (hi - lo);
+  });
+}
+
+int chefsi_static_scratch_bytes(const chefsi_handle_t* h, int32_t ns, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr || ns < 1) return CHEFSI_ERR_INVALID_ARG;
+  *bytes = (size_t)h->np_tot * (size_t)ns * (h->precision == CHEFSI_FP64 ? sizeof(double) : sizeof(float));
+  return CHEFSI_OK;
+}
+
+int chefsi_apply_h_static(chefsi_handle_t* h, const void* X, void* Y, int32_t ns, void* stream) {
+  return guarded(h, [&] {
+    check(X != nullptr && Y != nullptr && X != Y, "X and Y must be distinct device blocks");
+    check_ns(h, ns);
+    size_t need = 0;
+    (void)chefsi_static_scratch_bytes(h, ns, &need);
+    if (need > (size_t)CHEFSI_STATIC_SCRATCH_BYTES)
+      throw Error{CHEFSI_ERR_WORKSPACE, "np_tot x ns projector coefficients (" + std::to_string(need) +
+                                            " bytes) exceed the static scratch of " +
+                                            std::to_string((size_t)CHEFSI_STATIC_SCRATCH_BYTES) +
+                                            " bytes: call on fewer orbitals at a time"};
+    void* alpha = scratch_address(h->device);  // looked up at create; a table read here
+    hipStream_t s = (hipStream_t)stream;
+    // no event records either (profiling may create events): the call only enqueues kernels
+    const bool prof = h->prof_on;
+    h->prof_on = false;
+    struct Restore {
+      chefsi_handle* h;
+      bool v;
+      ~Restore() { h->prof_on = v; }
+    } restore{h, prof};
+    if (h->precision == CHEFSI_FP64)
+      apply_fused<double, double, double>(h, (const double*)X, nullptr, (double*)Y, ns, 1.0, 0.0, 0.0,
+                                          (double*)alpha, s);
+    else
+      apply_fused<float, float, float>(h, (const float*)X, nullptr, (float*)Y, ns, 1.0, 0.0, 0.0, (float*)alpha,
+                                       s);
   });
 }
 

@@ -1,0 +1,71 @@
+"""The allocation-free variant of H X (chefsi_apply_h_static) against chefsi_apply_h.
+
+Both run the same kernels; the static variant keeps the projector coefficients in the
+library's per-GPU static scratch.  Two calls in a row on one handle, the second with
+fewer orbitals (the scratch keeps the first call's contents), must each equal the
+workspace entry point bit for bit and the FP64 oracle within the H X tolerance; a
+request beyond the scratch is refused before any launch.
+"""
+import numpy as np
+import pytest
+
+from oracle.hamiltonian import apply_h
+from paper_2302_09708_amd import inputs
+from tests._gpu import dev, host, stencil_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    from paper_2302_09708_amd import chefsi
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    chefsi.load()
+    return chefsi
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_static_apply_h_equals_workspace_apply_h(cs, prec):
+    prob = inputs.small_problem(n=(26, 21, 19), h=(0.3, 0.28, 0.32), bc=(0, 1, 0), fd_order=12, n_atoms=7,
+                                nproj_per_atom=4, seed=41)
+    dt = "float64" if prec == "fp64" else "float32"
+    h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=9)
+    ws = cs.workspace(h, 9)
+    rng = np.random.default_rng(17)
+    for ns in (9, 4):  # second call smaller than the first
+        print(f"static apply_h: {prec} ns={ns}", flush=True)
+        x = rng.standard_normal((prob.nd, ns)).astype(dt)
+        X = dev(x, dt)
+        Y_ws = torch.empty_like(X)
+        Y_st = torch.full_like(X, float("nan"))
+        h.chefsi_apply_h(X, Y_ws, ns, ws)
+        h.chefsi_apply_h_static(X, Y_st, ns)
+        torch.cuda.synchronize()
+        assert torch.equal(Y_ws, Y_st), "static-scratch H X differs from the workspace entry point"
+        ref = apply_h(prob, x.astype(np.float64))
+        scale = stencil_scale(prob) * np.abs(x).max()
+        tol = 1e-12 * scale if prec == "fp64" else 2e-6 * scale
+        assert np.abs(host(Y_st) - ref).max() <= tol
+    assert h.chefsi_static_scratch_bytes(4) == prob.nproj.sum() * 4 * (8 if prec == "fp64" else 4)
+    h.close()
+
+
+def test_static_apply_h_refuses_requests_beyond_the_scratch(cs):
+    prob = inputs.small_problem(n=(28, 28, 28), n_atoms=200, nproj_per_atom=4, seed=5)
+    np_tot = int(prob.nproj.sum())
+    ns = cs.STATIC_SCRATCH_BYTES // (np_tot * 8) + 1  # one orbital more than fits (FP64)
+    assert ns <= prob.nd
+    h = cs.Handle(prob, precision=cs.FP64, max_ns=ns)
+    assert h.chefsi_static_scratch_bytes(ns) > cs.STATIC_SCRATCH_BYTES
+    X = torch.zeros(ns, prob.nd, dtype=torch.float64, device="cuda")
+    Y = torch.zeros_like(X)
+    with pytest.raises(cs.ChefsiError) as e:
+        h.chefsi_apply_h_static(X, Y, ns)
+    assert e.value.status == cs.ERR_WORKSPACE
+    # the handle stays usable: the largest request that fits runs
+    ns_fit = ns - 1
+    h.chefsi_apply_h_static(X[:ns_fit], Y[:ns_fit], ns_fit)
+    torch.cuda.synchronize()
+    h.close()
