@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6      # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TFS = 2500.0    # MI355X dense BF16 matrix
-KERNELS = ["hx_apply", "nl_project", "gram", "gram_reduce", "rotate", "dense_eig", "copy", "fp64_fallback_steps"]
+KERNELS = ["hx_apply", "nonlocal", "gram", "gram_reduce", "rotate", "dense_eig", "copy", "fp64_fallback_steps"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hx_apply_cfg2_fp64_traffic.txt")
 
 
@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--slots", type=int, default=4, help="cfg5: concurrent solves")
     p.add_argument("--calibration", type=int, default=16, help="cfg5: requests solved alone to set the rate")
     p.add_argument("--cpu-columns", type=int, default=8)
+    p.add_argument("--no-subrecords", action="store_true",
+                   help="skip the cfg3/cfg4 mixed and serving records after the headline")
+    p.add_argument("--serving-requests", type=int, default=48, help="requests of the serving record")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="after the timed steps, run one plain device copy of 1 GiB (counter calibration)")
     return p.parse_args()
@@ -61,48 +64,62 @@ def kernel_source_hash(name: str) -> str:
 
 
 def cpu_baseline(prob, cfg, ns_cols: int):
-    """The FP64 oracle on a bounded sample of one CheFSI iteration of this workload.
+    """The FP64 oracle timed on this host on a bounded sample of one CheFSI iteration of
+    this workload, on the workload's own inputs (seeded X0):
 
-    Sample: the filter (degree m) plus the extra H application on ``ns_cols`` of the
-    Ns columns (per-column cost is independent of the other columns), scaled by
-    Ns / ns_cols, plus the full-size projection and rotation products and the dense
-    generalized eigensolve on random data of the workload's shape."""
-    import scipy.linalg
+      * the filter (degree m) and the extra H X~ on ``ns_cols`` of the Ns columns, scaled
+        by Ns / ns_cols (the oracle applies H to each column independently, so this cost
+        is linear in Ns);
+      * the two Gram products, the dense generalized eigensolve and the rotation X~ Z~,
+        each run once in full on the whole block (X0 stands in for X~ and Y~, and its
+        Gram matrix plus a spread diagonal for H~: these costs do not depend on the
+        values);
+
+    plus, for scale, whole oracle iterations of the 24^3 workload (median of five)."""
     from oracle import chefsi as oc
-    from oracle.hamiltonian import apply_h
-    from paper_2302_09708_amd.inputs import initial_block
+    from paper_2302_09708_amd.inputs import CONFIGS, initial_block, make_problem
 
-    rng = np.random.default_rng(0)
+    from oracle.hamiltonian import apply_h
     lo, cut, hi = oc.spectral_bounds(prob)
-    x = initial_block(prob.nd, ns_cols, cfg.x_seed).T
+    x = initial_block(prob.nd, cfg.ns, cfg.x_seed).T   # Nd x Ns
+    xs = np.ascontiguousarray(x[:, :ns_cols])
     t0 = time.perf_counter()
-    xf = oc.chebyshev_filter(prob, x, cfg.degree, lo, cut, hi)
+    xf = oc.chebyshev_filter(prob, xs, cfg.degree, lo, cut, hi)
     apply_h(prob, xf)
     t_filter = (time.perf_counter() - t0) * cfg.ns / ns_cols
-    ns = cfg.ns
-    a = rng.standard_normal((prob.nd, ns))
-    b = rng.standard_normal((prob.nd, ns))
     t0 = time.perf_counter()
-    hs = a.T @ b
-    ms = a.T @ a
+    hs = x.T @ x
+    ms = x.T @ x
     t_proj = time.perf_counter() - t0
-    hs = 0.5 * (hs + hs.T)
-    ms = ms + prob.nd * np.eye(ns)
+    hs = 0.5 * (hs + hs.T) + np.diag(np.arange(cfg.ns, dtype=np.float64))
+    ms = 0.5 * (ms + ms.T)
     t0 = time.perf_counter()
-    d, z = scipy.linalg.eigh(hs, ms, type=1, driver="gvd")
+    d, z = oc.diagonalize(hs, ms)
     t_eig = time.perf_counter() - t0
     t0 = time.perf_counter()
-    a @ z
+    oc.rotate(x, z)
     t_rot = time.perf_counter() - t0
     total = t_filter + t_proj + t_eig + t_rot
+    # whole iterations of the small workload
+    c1 = CONFIGS["cfg1"]
+    p1 = make_problem(c1)
+    x1 = initial_block(p1.nd, c1.ns, c1.x_seed).T
+    l1, k1, h1 = oc.spectral_bounds(p1)
+    its = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        d1, x1 = oc.chefsi_step(p1, x1, c1.degree, l1, k1, h1)
+        its.append(time.perf_counter() - t0)
+        l1, k1 = float(d1[0]), float(d1[-1])
     cores = len(os.sched_getaffinity(0))
     return {
         "value": 1.0 / total, "unit": "iter/s", "cores": cores, "kind": "oracle",
-        "sample": (f"oracle filter (degree {cfg.degree}) + H X on {ns_cols} of {ns} columns scaled x{ns / ns_cols:g}"
-                   f" ({t_filter:.1f} s), full-size X^T Y and X^T X ({t_proj:.1f} s), dsygvd {ns} ({t_eig:.2f} s), "
-                   f"X Z ({t_rot:.1f} s) on random data of the {cfg.name} shape; NumPy stencil single-threaded, "
-                   f"BLAS/LAPACK on {cores} threads"),
+        "sample": (f"oracle on the {cfg.name} inputs: filter (degree {cfg.degree}) + H X on {ns_cols} of {cfg.ns} "
+                   f"columns scaled x{cfg.ns / ns_cols:g} ({t_filter:.1f} s); X^T Y and X^T X on the whole block "
+                   f"({t_proj:.1f} s); dsygvd {cfg.ns} ({t_eig:.2f} s); X Z ({t_rot:.2f} s); NumPy stencil "
+                   f"single-threaded, BLAS/LAPACK on {cores} threads; 24^3 workload whole iterations, median of 5"),
         "seconds_per_iter": total,
+        "cfg1_whole_iter_per_s": 1.0 / float(np.median(its)),
     }
 
 
@@ -165,6 +182,10 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
     ws = cs.workspace(h, ns)
     lo, cut, hi = h.chefsi_spectral_bounds()
     stream = torch.cuda.current_stream()
+    # one-time set-up: stencil tiling and projector split picked by timing (X is not changed)
+    t_tune = time.perf_counter()
+    tuned = h.chefsi_autotune(X, ns, ws, stream=stream)
+    tune_s = time.perf_counter() - t_tune
     for _ in range(warmup):
         d = h.chefsi_step(X, ns, m, lo, cut, hi, ws, stream=stream)
         lo, cut = float(d[0]), float(d[-1])
@@ -184,11 +205,14 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
         ms, n = h.chefsi_profile_read(kid)
         kern[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_launch_ms": ms / n if n else 0.0}
     h.chefsi_profile_reset()
+    ritz_steps = d
+    fallback_steps = kern["fp64_fallback_steps"]["launches_per_step"] * steps
     refine_ms = None
+    ritz_refined = None
     if prec == cs.MIXED:  # the once-per-solve FP64 refinement (filter + FP64 Rayleigh-Ritz), timed once
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        h.chefsi_refine_fp64(X, ns, ws, m, lo, cut, hi, stream=stream)
+        ritz_refined = h.chefsi_refine_fp64(X, ns, ws, m, lo, cut, hi, stream=stream)
         torch.cuda.synchronize()
         refine_ms = (time.perf_counter() - t1) * 1e3
     h.chefsi_profile_enable(False)
@@ -202,8 +226,13 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
            "hx_gbs": hx_bytes_step / (hx_ms * 1e-3) / 1e9, "hx_bytes_step": hx_bytes_step, "kernels": kern,
            "gemm": gemm_figures(prob.nd, ns, prec, kern["gram"]["ms_per_step"] + kern["gram_reduce"]["ms_per_step"],
                                 kern["rotate"]["ms_per_step"], prec == cs.FP64)}
+    out["ritz_steps"] = ritz_steps
+    out["stencil_choice"] = {"rows_per_thread": tuned[0], "row_groups": tuned[1], "projectors_in_stencil": tuned[2],
+                             "autotune_s": tune_s}
+    out["fallback_steps"] = int(round(fallback_steps))
     if refine_ms is not None:
         out["refine_ms"] = refine_ms
+        out["ritz_refined"] = ritz_refined
         # a solve of n_iter filter passes: n_iter - 1 mixed steps + the refinement
         out["solve_ms"] = (cfg.n_iter - 1) * out["ms_per_step"] + refine_ms
     else:
@@ -380,6 +409,64 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def workload_record(cs, name: str, steps: int, warmup: int, with_fp64: bool):
+    """A mixed-precision workload outside the headline's timed region: per-step time and
+    kernel split, stencil rate, split-bf16 MFMA utilisation, FP64 fallbacks, the FP64
+    refinement and how far it moves the Ritz values; optionally the FP64 path on the same
+    (device-drawn) X0."""
+    import torch
+    from paper_2302_09708_amd import inputs
+    cfg = inputs.CONFIGS[name]
+    t0 = time.perf_counter()
+    prob = inputs.make_problem(cfg)
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] {name}: Nd={prob.nd} Ns={cfg.ns} mixed ({setup_s:.1f} s to build the problem)",
+          file=sys.stderr, flush=True)
+    mixed = run_path(cs, prob, cfg, "mixed", steps, warmup, None)
+    k_chk = max(1, int(cfg.ns / 1.2))
+    moved = np.abs(mixed["ritz_refined"][:k_chk] - mixed["ritz_steps"][:k_chk])
+    rec = {
+        "workload": f"{name}: {'x'.join(map(str, cfg.n))} grid h={cfg.h[0]}, bc {''.join('PD'[b] for b in cfg.bc)}, "
+                    f"{cfg.n_atoms} atoms x {cfg.nproj_per_atom} projectors, Ns={cfg.ns}, degree {cfg.degree}, "
+                    f"X0 drawn on the device (seed {cfg.x_seed})",
+        "steps": steps, "warmup": warmup,
+        "mixed": {"iter_per_s": mixed["iter_per_s"], "ms_per_step": mixed["ms_per_step"],
+                  "hx_gbs": mixed["hx_gbs"], "hx_frac": mixed["hx_gbs"] / HBM_PEAK_GBS,
+                  "gemm_utilisation": mixed["gemm"]["utilisation"],
+                  "gram_executed_tflops": mixed["gemm"]["gram_executed_tflops"],
+                  "rotate_executed_tflops": mixed["gemm"]["rotate_executed_tflops"],
+                  "kernels_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in mixed["kernels"].items()},
+                  "stencil_choice": mixed["stencil_choice"],
+                  "fp64_fallback_steps": mixed["fallback_steps"],
+                  "refine_ms": mixed["refine_ms"],
+                  "ritz_lowest": float(mixed["ritz_refined"][0]),
+                  "refine_max_ritz_change_first_nchk": float(moved.max()), "n_chk": k_chk},
+    }
+    if with_fp64:
+        fp = run_path(cs, prob, cfg, "fp64", steps, warmup, None)
+        rec["fp64"] = {"iter_per_s": fp["iter_per_s"], "ms_per_step": fp["ms_per_step"], "hx_gbs": fp["hx_gbs"],
+                       "gemm_utilisation": fp["gemm"]["utilisation"],
+                       "kernels_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in fp["kernels"].items()}}
+        rec["mixed_over_fp64_step_speedup"] = mixed["iter_per_s"] / fp["iter_per_s"]
+    torch.cuda.empty_cache()
+    return rec
+
+
+def serving_record(args, n_req: int):
+    """A short serving stream (the cfg5 recipe with fewer requests) outside the timed steps."""
+    import io
+    import contextlib
+    a = argparse.Namespace(**vars(args))
+    a.requests, a.calibration = n_req, min(args.calibration, 8)
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        serving_bench(a)
+    r = json.loads(buf.getvalue().strip().splitlines()[-1])
+    return {k: r[k] for k in ("value", "unit", "p50_s", "p99_s", "mean_latency_s", "makespan_s", "failed_requests",
+                              "mean_solo_solve_s", "arrival_rate_per_s", "peak_concurrent")} | {
+        "requests": n_req, "slots": args.slots}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -435,6 +522,9 @@ def main():
                 "unit": "GB/s", "frac": main_run["hx_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": main_run["hx_bytes_step"] / hx_launches,
                 "avg_launch_ms": kern["hx_apply"]["avg_launch_ms"],
+                # the whole H application: stencil pass plus the projector gather and scatter
+                "with_nonlocal_gbs": main_run["hx_bytes_step"] / ((kern["hx_apply"]["ms_per_step"] +
+                                                                  kern["nonlocal"]["ms_per_step"]) * 1e-3) / 1e9,
                 "copy_gbs": cgbs, "frac_of_copy": main_run["hx_gbs"] / cgbs}
 
     out = {
@@ -459,6 +549,7 @@ def main():
         "hx_gbs": main_run["hx_gbs"],
         "gemm": g,
         "kernels": kern,
+        "stencil_choice": main_run["stencil_choice"],
         "solve_ms": main_run["solve_ms"],
         "lanczos_lam_nd": lz,
         "nonlocal_forces": fo,
@@ -476,10 +567,17 @@ def main():
             out["compare"]["refine_ms"] = other["refine_ms"]
     if "refine_ms" in main_run:
         out["refine_ms"] = main_run["refine_ms"]
+    if not args.no_subrecords and cfg.name == "cfg2":
+        # the configurations the mixed-precision target is about, outside the timed steps
+        out["cfg3"] = workload_record(cs, "cfg3", steps=3, warmup=1, with_fp64=True)
+        out["cfg4"] = workload_record(cs, "cfg4", steps=2, warmup=1, with_fp64=False)
+        print(f"[bench] serving: {args.serving_requests} requests", file=sys.stderr, flush=True)
+        out["cfg5_serving"] = serving_record(args, args.serving_requests)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(prob, cfg, args.cpu_columns)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                     "cfg1_whole_iter_per_s")}
         out["speedup_vs_cpu_oracle"] = out["value"] / cb["value"]
     print(json.dumps(out), flush=True)
 

@@ -143,11 +143,31 @@ int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
  * for one row per thread, 512 otherwise).  chefsi_set_stencil_tiling(h, 0, 0) restores the
  * library's choice; another pair replaces it (the projector records are rebuilt) and
  * returns CHEFSI_ERR_INVALID_ARG, keeping the current tiling, when it does not fit the
- * grid (rows_per_thread 1..4).  Results agree across tilings to rounding (each point
+ * grid (rows_per_thread 1..2).  Results agree across tilings to rounding (each point
  * sums the same terms; the last bits can differ).  For tuning and tests.
  * chefsi_get_stencil_tiling writes {rows_per_thread, row_groups, tile rows, halo values
  * per thread} to tiling[0..3]. */
 int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups);
+/* Where the projector term of H X is added (Sec. 2.1, third bullet; results agree to
+ * rounding).  in_stencil = 1 (default): points inside at most four projector entries
+ * take it inside the stencil pass from per-point records, the others in a separate
+ * scatter pass; in_stencil = 0: every touched point takes it in the scatter pass (one
+ * thread per point and eight orbitals, the point's entries read once per eight
+ * orbitals), and the stencil pass runs without records.  Rebuilds the handle's tables;
+ * for tuning and tests, not while calls on the handle are in flight. */
+int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
+
+/* Picks the stencil tiling and the projector split by timing them (the planner's
+ * tilings of at least r + 1 rows, each with the projector term in the stencil pass for
+ * points inside at most four entries and with every term in the scatter pass): three
+ * filter-form H applications per candidate on the first min(ns, 256) orbitals of the
+ * device block X (read only; the workspace block takes the results), on `stream`, which
+ * the call synchronises.  Keeps the fastest and, when choice is not NULL, writes
+ * {rows per thread, row groups, in_stencil} to choice[0..2].  Results after tuning agree
+ * with the untuned ones to rounding (the same terms summed in another order).  ws as for
+ * chefsi_apply_h with this ns.  A one-time set-up call, like a library benchmark mode. */
+int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
+                    int32_t* choice);
 int chefsi_get_stencil_tiling(const chefsi_handle_t* h, int32_t* tiling);
 
 /* Rigorous filter bounds for the first step (the paper names lam_hi the

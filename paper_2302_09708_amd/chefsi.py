@@ -46,7 +46,8 @@ EXPORTS = (
     "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
     "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
     "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling", "chefsi_nonlocal_stress",
-    "chefsi_static_scratch_bytes", "chefsi_apply_h_static",
+    "chefsi_static_scratch_bytes", "chefsi_apply_h_static", "chefsi_set_projector_pass",
+    "chefsi_autotune",
 )
 
 
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.chefsi_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_handle_bytes.argtypes = [vp, C.POINTER(sz)]
     lib.chefsi_set_stencil_tiling.argtypes = [vp, i32, i32]
+    lib.chefsi_set_projector_pass.argtypes = [vp, i32]
+    lib.chefsi_autotune.argtypes = [vp, vp, i32, vp, sz, vp, C.POINTER(C.c_int32)]
     lib.chefsi_get_stencil_tiling.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.chefsi_spectral_bounds.argtypes = [vp, pd, pd, pd]
     lib.chefsi_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
@@ -311,6 +314,15 @@ class Handle:
 
     def chefsi_set_stencil_tiling(self, rows_per_thread: int, row_groups: int) -> None:
         self._check(self._lib.chefsi_set_stencil_tiling(self.h, rows_per_thread, row_groups))
+
+    def chefsi_set_projector_pass(self, in_stencil: bool) -> None:
+        self._check(self._lib.chefsi_set_projector_pass(self.h, 1 if in_stencil else 0))
+
+    def chefsi_autotune(self, X, ns, ws, ws_bytes=None, stream=None) -> Tuple[int, int, bool]:
+        c = (C.c_int32 * 3)()
+        self._check(self._lib.chefsi_autotune(self.h, _ptr(X), int(ns), _ptr(ws), self._wsb(ws, ws_bytes),
+                                              _stream(stream), c))
+        return int(c[0]), int(c[1]), bool(c[2])
 
     def chefsi_get_stencil_tiling(self) -> Tuple[int, int, int, int]:
         t = (C.c_int32 * 4)()

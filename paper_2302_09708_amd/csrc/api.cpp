@@ -159,6 +159,10 @@ struct chefsi_handle {
   int n_pts = 0;     // scatter records
   int n_hxrec = 0;   // stencil-pass records
   size_t hx_rec_bytes = 0;   // device bytes of the stencil-pass records
+  size_t scatter_bytes = 0;  // device bytes of the scatter records and entries
+  // points in at most this many projector entries take their projector term inside the
+  // stencil pass (4: the record width); the others go to the scatter pass (0: all)
+  int rec_max = 4;
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -1010,7 +1014,7 @@ void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
   std::vector<int> rptr(nkeys + 1, 0);
   for (int64_t i = 0; i < nd; ++i) {
     const int n = cnt[i + 1] - cnt[i];
-    if (n >= 1 && n <= 4) rptr[key_of(i) + 1] += 1;
+    if (n >= 1 && n <= h->rec_max) rptr[key_of(i) + 1] += 1;
   }
   for (int64_t k = 0; k < nkeys; ++k) rptr[k + 1] += rptr[k];
   const int nrec = rptr[nkeys];
@@ -1021,7 +1025,7 @@ void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
   std::vector<int> rfill(rptr.begin(), rptr.end() - 1);
   for (int64_t i = 0; i < nd; ++i) {
     const int b = cnt[i], n = cnt[i + 1] - b;
-    if (n < 1 || n > 4) continue;
+    if (n < 1 || n > h->rec_max) continue;
     const int r = rfill[key_of(i)]++;
     const int x = (int)(i % nx), y = (int)((i / nx) % ny);
     int col[4] = {0, 0, 0, 0};
@@ -1059,6 +1063,57 @@ void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
   h->hx_rec32 = n32;
   h->n_hxrec = nrec;
   h->hx_plan = hp;
+}
+
+// Scatter-pass records for the points in more than rec_max projector entries (all touched
+// points when rec_max is 0): one record {point, first entry, entry count, 0} each, entries
+// in atom order padded with zeros to a multiple of 4; replaces the handle's current ones.
+void build_scatter_records(chefsi_handle* h) {
+  std::vector<int4> recs;
+  std::vector<int> ecol;
+  std::vector<double> evals;
+  for (int64_t i = 0; i < h->nd; ++i) {
+    const int b = h->pt_cnt[i], n = h->pt_cnt[i + 1] - b;
+    if (n <= h->rec_max) continue;
+    recs.push_back(make_int4((int)i, (int)ecol.size(), n, 0));
+    for (int k = b; k < b + n; ++k) {
+      ecol.push_back(h->pt_col[k]);
+      evals.push_back(h->pt_val[k]);
+    }
+    while (ecol.size() % 4) {
+      ecol.push_back(0);
+      evals.push_back(0.0);
+    }
+  }
+  check(ecol.size() < ((size_t)1 << 31), "too many projector entries");
+  int4* rec = nullptr;
+  int* col = nullptr;
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  try {
+    if (!recs.empty()) {
+      rec = upload(h, recs.data(), recs.size());
+      col = upload(h, ecol.data(), ecol.size());
+      v64 = upload(h, evals.data(), evals.size());
+      std::vector<float> ev32(evals.begin(), evals.end());
+      v32 = upload(h, ev32.data(), ev32.size());
+    }
+  } catch (...) {
+    for (void* q : {(void*)rec, (void*)col, (void*)v64, (void*)v32})
+      if (q) (void)hipFree(q);
+    throw;
+  }
+  for (void* q : {(void*)h->rec, (void*)h->ent_col, (void*)h->ent_val64, (void*)h->ent_val32})
+    if (q) (void)hipFree(q);
+  h->device_bytes -= h->scatter_bytes;
+  h->scatter_bytes = recs.empty() ? 0
+                                  : recs.size() * sizeof(int4) + ecol.size() * (sizeof(int) + sizeof(double) +
+                                                                                sizeof(float));
+  h->rec = rec;
+  h->ent_col = col;
+  h->ent_val64 = v64;
+  h->ent_val32 = v32;
+  h->n_pts = (int)recs.size();
 }
 
 void release(chefsi_handle* h) {
@@ -1152,7 +1207,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
     check(max_ns >= 1 && (int64_t)max_ns <= nd, "max_ns must satisfy 1 <= max_ns <= Nd");
     for (int eb : {4, 8})
       check(plan_hx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2, eb, 0, 0).ok,
-            "grid too wide in x for the stencil tiling (needs 2r*nx <= 4*blocksize)");
+            "grid too wide in x for the stencil tiling (the halo rows of a tile need at most four values per thread)");
     h->nd = nd;
     h->max_ns = max_ns;
     h->dv = grid->h[0] * grid->h[1] * grid->h[2];
@@ -1250,33 +1305,7 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       h->pt_val = std::move(eval);
       check(h->np_tot < 65536, "more than 65535 projectors");
       build_hx_records(h, h->hx_plan);
-      // points with more than four entries: one scatter record {point, first entry, entry
-      // count, 0} each, entries in atom order padded with zeros to a multiple of 4
-      std::vector<int4> recs;
-      std::vector<int> ecol;
-      std::vector<double> evals;
-      for (int64_t i = 0; i < nd; ++i) {
-        const int b = h->pt_cnt[i], n = h->pt_cnt[i + 1] - b;
-        if (n <= 4) continue;
-        recs.push_back(make_int4((int)i, (int)ecol.size(), n, 0));
-        for (int k = b; k < b + n; ++k) {
-          ecol.push_back(h->pt_col[k]);
-          evals.push_back(h->pt_val[k]);
-        }
-        while (ecol.size() % 4) {
-          ecol.push_back(0);
-          evals.push_back(0.0);
-        }
-      }
-      check(ecol.size() < ((size_t)1 << 31), "too many projector entries");
-      h->n_pts = (int)recs.size();
-      if (!recs.empty()) {
-        h->rec = upload(h, recs.data(), recs.size());
-        h->ent_col = upload(h, ecol.data(), ecol.size());
-        h->ent_val64 = upload(h, evals.data(), evals.size());
-        std::vector<float> ev32(evals.begin(), evals.end());
-        h->ent_val32 = upload(h, ev32.data(), ev32.size());
-      }
+      build_scatter_records(h);
       h->supp_off = upload(h, soff.data(), soff.size());
       h->supp_idx = upload(h, h->supp_idx_h.data(), h->supp_idx_h.size());
       h->chi_off = upload(h, coff.data(), coff.size());
@@ -2021,7 +2050,7 @@ int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void
 
 int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups) {
   return guarded(h, [&] {
-    check(rows_per_thread >= 0 && rows_per_thread <= 4 && row_groups >= 0, "tiling parameters out of range");
+    check(rows_per_thread >= 0 && rows_per_thread <= 2 && row_groups >= 0, "tiling parameters out of range");
     check((rows_per_thread == 0) == (row_groups == 0), "give both tiling parameters, or neither");
     const int eb = h->precision == CHEFSI_FP64 ? 8 : 4;
     const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, eb, rows_per_thread, row_groups);
@@ -2030,6 +2059,117 @@ int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32
       build_hx_records(h, p);
     else
       h->hx_plan = p;
+  });
+}
+
+// Average time of one filter-form launch sequence (projector gather, stencil pass with the
+// three-term update, scatter pass) on the first ns columns of X, written into the workspace
+// block (X is not modified).
+extern "C++" {
+template <typename T>
+static float time_filter_launch(chefsi_handle* h, const T* X, T* B, int ns, T* alpha, hipStream_t s,
+                                hipEvent_t e0, hipEvent_t e1) {
+  constexpr int kWarm = 1, kRuns = 3;
+  for (int i = 0; i < kWarm; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s);
+  HIP_TRY(hipEventRecord(e0, s));
+  for (int i = 0; i < kRuns; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s);
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  return ms / kRuns;
+}
+}  // extern "C++"
+
+int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
+                    int32_t* choice) {
+  return guarded(h, [&] {
+    check(X != nullptr, "X is NULL");
+    check_ns(h, ns);
+    WsLayout L;
+    check_ws(h, ns, ws, ws_bytes, L);
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = std::min(ns, 256);  // orbitals timed: the per-orbital work is the same for all
+    const int eb = h->precision == CHEFSI_FP64 ? 8 : 4;
+    const int nx = h->n[0], ny = h->n[1];
+    // candidate tilings: every row count per thread and row-group count the planner accepts,
+    // tall tiles only (at least r + 1 rows, or the whole y extent)
+    std::vector<HxPlan> cands;
+    for (int py = 1; py <= 2; ++py)
+      for (int nyg = 1; nx * nyg <= hx_max_threads(py); ++nyg) {
+        if (py * nyg < std::min(h->radius + 1, ny) || py * nyg > ny + 2 * h->radius) continue;
+        const HxPlan p = plan_hx(nx, ny, h->n[2], 1, h->radius, eb, py, nyg);
+        if (p.ok) cands.push_back(p);
+      }
+    check(!cands.empty(), "no stencil tiling fits this grid");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct Events {
+      hipEvent_t a, b;
+      ~Events() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } ev{e0, e1};
+    const bool prof = h->prof_on;
+    h->prof_on = false;
+    float best = 1e30f;
+    int best_mode = h->rec_max, best_c = 0;
+    const int modes[2] = {4, 0};
+    for (int mode : modes) {
+      if (h->np_tot == 0 && mode == 0) continue;
+      if (h->rec_max != mode) {
+        h->rec_max = mode;
+        build_scatter_records(h);
+      }
+      for (size_t c = 0; c < cands.size(); ++c) {
+        if (h->np_tot > 0)
+          build_hx_records(h, cands[c]);
+        else
+          h->hx_plan = cands[c];
+        float ms;
+        if (h->precision == CHEFSI_FP64)
+          ms = time_filter_launch<double>(h, (const double*)X, at<double>(ws, L.bufB), nt, at<double>(ws, L.alpha),
+                                          s, e0, e1);
+        else
+          ms = time_filter_launch<float>(h, (const float*)X, at<float>(ws, L.bufB), nt, at<float>(ws, L.alpha), s,
+                                         e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_mode = mode;
+          best_c = (int)c;
+        }
+      }
+    }
+    h->prof_on = prof;
+    if (h->rec_max != best_mode) {
+      h->rec_max = best_mode;
+      build_scatter_records(h);
+    }
+    if (h->np_tot > 0)
+      build_hx_records(h, cands[best_c]);
+    else
+      h->hx_plan = cands[best_c];
+    if (choice) {
+      choice[0] = cands[best_c].py;
+      choice[1] = cands[best_c].nyg;
+      choice[2] = best_mode > 0 ? 1 : 0;
+    }
+  });
+}
+
+int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil) {
+  return guarded(h, [&] {
+    check(in_stencil == 0 || in_stencil == 1, "in_stencil must be 0 or 1");
+    const int want = in_stencil ? 4 : 0;
+    if (want == h->rec_max || h->np_tot == 0) {
+      h->rec_max = want;
+      return;
+    }
+    h->rec_max = want;
+    build_hx_records(h, h->hx_plan);
+    build_scatter_records(h);
   });
 }
 

@@ -16,6 +16,7 @@ constexpr int kHxMaxThreads = 512;  // widest supported x row (one thread per x 
 // stencil threads per block for PY rows per thread (1024 keeps 128 VGPRs per lane, 512 keeps 256)
 constexpr int hx_max_threads(int py) { return py == 1 ? 1024 : 512; }
 constexpr int kHxMaxHalo = 4;            // halo values each stencil thread stages per plane
+constexpr int kHxDummy = 64;             // per-lane dummy LDS slots after each stencil buffer
 constexpr size_t kHxMaxLds = 96 * 1024;  // dynamic LDS of one stencil block (gfx950: 160 KB per CU)
 
 // ---------------------------------------------------------------------------
@@ -59,7 +60,16 @@ struct HxArgs {
   int nzc;   // z chunks
   int64_t nblocks;  // nty * nzc * ns
   int per_xcd;      // blocks per XCD after padding the grid to a multiple of 8
+  int pitch;        // LDS row pitch in elements (hx_pitch)
 };
+
+// LDS row pitch of the stencil tile: nx plus a gap of at least 2r columns (the x halo) that
+// is a whole multiple of 256 bytes of elements, so the lanes of a wave that straddle two
+// tile rows fall on distinct LDS banks (a gap of 2r alone put them two to a bank).
+__host__ __device__ inline int hx_pitch(int nx, int radius, int elem_bytes) {
+  const int g = 256 / elem_bytes;
+  return nx + ((2 * radius + g - 1) / g) * g;
+}
 
 struct HxPlan {
   bool ok = false;  // false: no tiling fits this grid
@@ -70,7 +80,7 @@ struct HxPlan {
   int zc = 1;
   int nzc = 1;
   int threads = 64;
-  int kh = 4;        // halo values each thread stages per plane (2 or 4)
+  int kh = 4;        // halo values each thread stages per plane (2, 3 or 4)
   size_t lds_tile_bytes = 0;  // two tile planes
 };
 

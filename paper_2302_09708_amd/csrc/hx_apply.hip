@@ -24,11 +24,14 @@
 //   * the block marches through z.  Each thread keeps its 2r+1 z-neighbours in a
 //     register queue (the z part never touches LDS) and fetches the next plane one
 //     iteration ahead.  The current plane of the tile plus r halo rows above and
-//     below sits in LDS, double-buffered so one barrier per plane suffices; x
-//     neighbours wrap inside the row (periodic) or read as zero (Dirichlet), so whole
-//     rows need no x halo; y neighbours are read once per column and reused by the
-//     PY rows a thread owns.  The kernel is kept lean in registers: on this path
-//     occupancy hides memory latency better than deeper per-thread prefetch;
+//     below sits in LDS, double-buffered so one barrier per plane suffices; each LDS
+//     row carries r halo columns on either side (periodic copies, or zeros for a
+//     Dirichlet x), so every x neighbour is a fixed offset.  Besides its own elements
+//     a thread stages KH values of the plane's halo rows and periodic x copies, each
+//     read straight from its (wrapped) source; y neighbours are read once per column
+//     and reused by the PY rows a thread owns.  The kernel is kept lean in registers:
+//     on this path occupancy hides memory latency better than deeper per-thread
+//     prefetch;
 //   * global reads are buffer loads: a Dirichlet ghost is an out-of-range offset,
 //     which returns zero without touching memory, so the loads need no branches.
 #include "common.h"
@@ -49,12 +52,6 @@ __device__ __forceinline__ int row_offset(int x, int gy, int nx, int ny, int per
   if (per_y) return x + nx * wrap_index(gy, ny);
   return (gy < 0 || gy >= ny) ? -1 : x + nx * gy;
 }
-
-// Periodic halo copies of element x in a tile row (pitch nx + 2r, element x at column
-// r + x; nx >= r): the right halo holds x < r at column r + nx + x, the left halo holds
-// x >= nx - r at column x - nx + r (with nx < 2r a point has both copies); -1 = none.
-__device__ __forceinline__ int xcopy_right(int x, int nx, int r) { return x < r ? r + nx + x : -1; }
-__device__ __forceinline__ int xcopy_left(int x, int nx, int r) { return x >= nx - r ? x - nx + r : -1; }
 
 // Offset of plane pz, or -1 for a Dirichlet zero plane.
 __device__ __forceinline__ int plane_offset(int pz, int nplane, int nz, int per_z) {
@@ -135,8 +132,46 @@ __device__ __forceinline__ void load_rec(__amdgpu_buffer_rsrc_t r, unsigned voff
   }
 }
 
+// Number of LDS slots a block stages per plane besides its own body elements: the r halo
+// rows above and below the tile (nx + 2r columns when x is periodic, the nx interior
+// columns when it is not) and, when x is periodic, the r wrapped copies on each side of
+// every body row.  (Dirichlet x halo columns are zeros written once.)
+__host__ __device__ inline int hx_halo_slots(int nx, int ty, int radius, int per_x) {
+  return 2 * radius * (per_x ? nx + 2 * radius : nx) + (per_x ? ty * 2 * radius : 0);
+}
+
+// Slot e of a plane's staged set: LDS destination (row-major with the given pitch, element
+// x of a row at column r + x) and source row offset inside the plane (x added; -1 for a
+// zero value).
+__device__ __forceinline__ void halo_slot(int e, int nx, int ny, int ty, int y0, int radius, int pitch, int per_x,
+                                          int per_y, int& dst, int& src) {
+  const int w = per_x ? nx + 2 * radius : nx;
+  int yy, c;
+  if (e < 2 * radius * w) {  // halo rows: local rows [0, r) and [r + ty, ty + 2r)
+    const int hr = e / w;
+    c = e % w + (per_x ? 0 : radius);
+    yy = hr < radius ? hr : hr + ty;
+  } else {  // periodic x copies of the body rows: columns [0, r) and [r + nx, nx + 2r)
+    const int f = e - 2 * radius * w;
+    const int cc = f % (2 * radius);
+    c = cc < radius ? cc : nx + cc;
+    yy = radius + f / (2 * radius);
+  }
+  int gx = c - radius;
+  if (gx < 0) gx += nx;  // only reached with periodic x (nx >= r: one wrap)
+  if (gx >= nx) gx -= nx;
+  dst = yy * pitch + c;
+  src = row_offset(gx, y0 - radius + yy, nx, ny, per_y);
+}
+
 // one row per thread fits 128 VGPRs, so its blocks may hold 1024 threads (taller tiles,
-// fewer halo rows per output row); two or more rows per thread keep 256 VGPRs and 512
+// fewer halo rows per output row); two rows per thread keep 256 VGPRs and 512.
+//
+// The plane loop is kept free of divergent branches and of per-plane index arithmetic:
+// every lane writes its LDS slots unconditionally (a lane with nothing to stage writes a
+// dummy slot of its own past the end of the buffer), zero planes (Dirichlet z) are read
+// through a resource with no records selected on the scalar unit, and the plane indices
+// advance by one with a compare-and-reset wrap.
 template <typename TI, typename TC, typename TO, int R, int PY, int KH, bool NL>
 __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI, TC, TO> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -144,6 +179,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
+  const int lane = tid & 63;
 
   // hardware deals consecutive block ids to the 8 XCDs in turn
   const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
@@ -161,27 +197,31 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
 
   const int plane_pts = a.ty * nx;
   // LDS tile rows carry r halo columns on each side (periodic copies, or zeros for a
-  // Dirichlet x), so every x neighbour is a fixed offset from the thread's own element
-  const int pitch = nx + 2 * R;
+  // Dirichlet x), so every x neighbour is a fixed offset from the thread's own element;
+  // each buffer ends with 64 dummy slots (one per lane) for writes that have no target
+  const int pitch = a.pitch;
   const int tile_elems = (a.ty + 2 * R) * pitch;
+  const int tile_buf = tile_elems + kHxDummy;
+  const int nl_buf = plane_pts + kHxDummy;
   // LDS: [record offsets of this chunk][alpha row][projector term x2] (NL only) [tile plane x2]
   int* s_rp = reinterpret_cast<int*>(lds_raw);
   const int rp_slots = NL ? ((nzl + 1 + 3) & ~3) : 0;
   TC* s_alpha = reinterpret_cast<TC*>(s_rp + rp_slots);
   const int al_slots = NL ? ((a.np_tot + 1) & ~1) : 0;
   TC* s_nl = s_alpha + al_slots;
-  TI* s_tile = reinterpret_cast<TI*>(s_nl + (NL ? 2 * plane_pts : 0));
+  TI* s_tile = reinterpret_cast<TI*>(s_nl + (NL ? 2 * nl_buf : 0));
   typedef __attribute__((address_space(3))) const TC lds_tc;  // keeps the alpha reads ds_read
   lds_tc* l_alpha = (lds_tc*)s_alpha;
 
   const bool active = tid < nx * a.nyg;
   const int x = active ? tid % nx : 0;
   const int ly0 = active ? (tid / nx) * PY : 0;
-  const int xcr = active && a.per_x ? xcopy_right(x, nx, R) : -1;  // the thread's periodic x copies
-  const int xcl = active && a.per_x ? xcopy_left(x, nx, R) : -1;
   const int nplane = nx * ny;
   const TI* xv = a.x + vec * a.nd;
   const int xbytes = (int)(a.nd * (int64_t)sizeof(TI));
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(xv, xbytes);
+  const __amdgpu_buffer_rsrc_t rz = make_rsrc(xv, 0);  // no records: every load reads zero
+  const unsigned xplane_bytes = (unsigned)nplane * (unsigned)sizeof(TI);
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(a.veff, a.nd * (int64_t)sizeof(TC));
   // with no previous iterate the resource has no records: its loads read zero
   const bool has_prev = a.prev != nullptr;
@@ -198,7 +238,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     const TC* g_alpha = a.alpha + vec * a.np_tot;
     for (int i = tid; i <= nzl; i += nthr) s_rp[i] = a.rec_ptr[tile * nz + z0 + i];
     for (int i = tid; i < a.np_tot; i += nthr) s_alpha[i] = g_alpha[i];
-    for (int i = tid; i < 2 * plane_pts; i += nthr) s_nl[i] = TC(0);
+    for (int i = tid; i < 2 * nl_buf; i += nthr) s_nl[i] = TC(0);
     __syncthreads();
     const int rb = __builtin_amdgcn_readfirstlane(s_rp[0]), re = __builtin_amdgcn_readfirstlane(s_rp[1]);
 #pragma unroll
@@ -209,53 +249,37 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     }
   }
 
-  int roff[PY];  // offset of the thread's rows inside a plane, -1 for a zero row
-  bool valid[PY];
+  // the thread's rows: plane offset (kOOB lane offsets for zero rows and rows past ny) and
+  // LDS slot (a dummy slot for idle lanes)
+  unsigned vq[PY], vv[PY], vp[PY];
+  int sown[PY];
 #pragma unroll
   for (int j = 0; j < PY; ++j) {
     const int gy = y0 + ly0 + j;
-    roff[j] = active ? row_offset(x, gy, nx, ny, a.per_y) : -1;
-    valid[j] = active && gy < ny;
+    const int ro_ = active ? row_offset(x, gy, nx, ny, a.per_y) : -1;
+    const bool valid = active && gy < ny;
+    vq[j] = lane_off<TI>(ro_);
+    vv[j] = lane_off<TC>(valid ? ro_ : -1);
+    vp[j] = lane_off<TO>(valid ? ro_ : -1);
+    sown[j] = active ? (R + ly0 + j) * pitch + R + x : tile_elems + lane;
   }
-  // halo rows (local rows [0, R) and [R + ty, ty + 2R)): source offset, LDS slot and the
-  // slots of its periodic x copies
-  int hoff[KH], hdst[KH], hdr[KH], hdl[KH];
+  // staged slots (halo rows and periodic x copies): LDS slot and source lane offset
+  int sdst[KH];
+  unsigned vh[KH];
   {
-    const int nhalo = 2 * R * nx;
+    const int nslots = hx_halo_slots(nx, a.ty, R, a.per_x);
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
       const int e = tid + k * nthr;
-      hoff[k] = -1;
-      hdst[k] = -1;
-      hdr[k] = -1;
-      hdl[k] = -1;
-      if (e < nhalo) {
-        const int hr = e / nx, hxx = e % nx;
-        const int yy = hr < R ? hr : hr + a.ty;
-        hoff[k] = row_offset(hxx, y0 - R + yy, nx, ny, a.per_y);
-        hdst[k] = yy * pitch + R + hxx;
-        if (a.per_x) {
-          const int cr = xcopy_right(hxx, nx, R), cl = xcopy_left(hxx, nx, R);
-          hdr[k] = cr >= 0 ? yy * pitch + cr : -1;
-          hdl[k] = cl >= 0 ? yy * pitch + cl : -1;
-        }
-      }
+      int dst = tile_elems + lane, src = -1;
+      if (e < nslots) halo_slot(e, nx, ny, a.ty, y0, R, pitch, a.per_x, a.per_y, dst, src);
+      sdst[k] = dst;
+      vh[k] = lane_off<TI>(src);
     }
   }
 
-  // lane byte offsets inside a plane: the thread's rows of x (vq), Veff (vv) and prev (vp)
-  // (kOOB for zero rows and rows past ny), and its halo values (vh)
-  unsigned vq[PY], vv[PY], vp[PY], vh[KH];
-#pragma unroll
-  for (int j = 0; j < PY; ++j) {
-    vq[j] = lane_off<TI>(roff[j]);
-    vv[j] = lane_off<TC>(valid[j] ? roff[j] : -1);
-    vp[j] = lane_off<TO>(valid[j] ? roff[j] : -1);
-  }
-#pragma unroll
-  for (int k = 0; k < KH; ++k) vh[k] = lane_off<TI>(hoff[k]);
-
-  // q[s][j] = plane (z - R + s); pf = plane z + R (fetched one plane ahead); hp = halo of plane z
+  // q[s][j] = plane (z - R + s); pf = plane z + R (fetched one plane ahead); hp = staged
+  // values of plane z
   TI q[Q][PY], pf[PY], hp[KH];
 #pragma unroll
   for (int j = 0; j < PY; ++j) q[0][j] = TI(0);
@@ -278,15 +302,24 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     const int nrows = 2 * (a.ty + 2 * R);
     for (int i = tid; i < nrows * 2 * R; i += nthr) {
       const int row = i / (2 * R), c = i % (2 * R);
-      s_tile[row * pitch + (c < R ? c : nx + c)] = TI(0);
+      const int buf = row / (a.ty + 2 * R), rr = row % (a.ty + 2 * R);
+      s_tile[buf * tile_buf + rr * pitch + (c < R ? c : nx + c)] = TI(0);
     }
   }
 
+  // planes fetched inside the loop: the queue's z + R + 1 and the staged set's z + 1,
+  // advanced by one per plane (wrapped when z is periodic; a Dirichlet plane at or past
+  // nz reads zero)
+  int pb = z0 + R + 1, ph = z0 + 1;
+  if (a.per_z) {
+    pb %= nz;
+    ph %= nz;
+  }
   for (int zl = 0; zl < nzl; ++zl) {
     const int z = z0 + zl;
-    TI* tl = s_tile + (zl & 1) * tile_elems;
+    TI* tl = s_tile + (zl & 1) * tile_buf;
+    const bool more = zl + 1 < nzl;
     if (NL) {  // records of plane zl + 1
-      const bool more = zl + 1 < nzl;
       const int rb = more ? __builtin_amdgcn_readfirstlane(s_rp[zl + 1]) : 0;
       const int re = more ? __builtin_amdgcn_readfirstlane(s_rp[zl + 2]) : 0;
 #pragma unroll
@@ -298,12 +331,13 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
     }
     // Veff and previous iterate of this plane, used at the end of the iteration
     TC cv[PY], cp[PY];
+    const unsigned zo = (unsigned)(nplane * z);
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
-      cv[j] = bload<TC>(rv, vv[j], (unsigned)(nplane * z) * (unsigned)sizeof(TC));
-      cp[j] = TC(bload<TO>(rp, vp[j], (unsigned)(nplane * z) * (unsigned)sizeof(TO)));
+      cv[j] = bload<TC>(rv, vv[j], zo * (unsigned)sizeof(TC));
+      cp[j] = TC(bload<TO>(rp, vp[j], zo * (unsigned)sizeof(TO)));
     }
-    // advance the queue; fetch plane z+R+1
+    // advance the queue; fetch plane z + R + 1
 #pragma unroll
     for (int s = 0; s < Q - 1; ++s)
 #pragma unroll
@@ -311,84 +345,81 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
 #pragma unroll
     for (int j = 0; j < PY; ++j) q[Q - 1][j] = pf[j];
     {
-      const int po = zl + 1 < nzl ? plane_offset(z + R + 1, nplane, nz, a.per_z) : -1;
+      const bool ok = more && pb < nz;
+      const __amdgpu_buffer_rsrc_t r = ok ? rx : rz;
+      const unsigned so = ok ? (unsigned)pb * xplane_bytes : 0u;
 #pragma unroll
-      for (int j = 0; j < PY; ++j) pf[j] = pload<TI>(xv, xbytes, vq[j], po);
+      for (int j = 0; j < PY; ++j) pf[j] = bload<TI>(r, vq[j], so);
     }
-    // stage plane z in LDS (and the periodic x copies); fetch the halo of plane z+1
-    if (active) {
+    // stage plane z in LDS; fetch the staged set of plane z + 1
 #pragma unroll
-      for (int j = 0; j < PY; ++j) {
-        tl[(R + ly0 + j) * pitch + R + x] = q[R][j];
-        if (xcr >= 0) tl[(R + ly0 + j) * pitch + xcr] = q[R][j];
-        if (xcl >= 0) tl[(R + ly0 + j) * pitch + xcl] = q[R][j];
-      }
-    }
+    for (int j = 0; j < PY; ++j) tl[sown[j]] = q[R][j];
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      if (hdst[k] >= 0) tl[hdst[k]] = hp[k];
-      if (hdr[k] >= 0) tl[hdr[k]] = hp[k];
-      if (hdl[k] >= 0) tl[hdl[k]] = hp[k];
-    }
+    for (int k = 0; k < KH; ++k) tl[sdst[k]] = hp[k];
     {
-      const int po = zl + 1 < nzl ? plane_offset(z + 1, nplane, nz, a.per_z) : -1;
+      const bool ok = more && ph < nz;
+      const __amdgpu_buffer_rsrc_t r = ok ? rx : rz;
+      const unsigned so = ok ? (unsigned)ph * xplane_bytes : 0u;
 #pragma unroll
-      for (int k = 0; k < KH; ++k) hp[k] = pload<TI>(xv, xbytes, vh[k], po);
+      for (int k = 0; k < KH; ++k) hp[k] = bload<TI>(r, vh[k], so);
     }
-    TC* nla = s_nl + ((zl & 1) ? plane_pts : 0);
+    ++pb;
+    ++ph;
+    if (a.per_z) {
+      pb = pb == nz ? 0 : pb;
+      ph = ph == nz ? 0 : ph;
+    }
+    TC* nla = s_nl + (zl & 1) * nl_buf;
     if (NL) {  // projector term of plane zl into its (zeroed) accumulator, one writer per point
       const int nrec = s_rp[zl + 1] - s_rp[zl];
 #pragma unroll
       for (int r = 0; r < PY; ++r) {
-        if (tid + r * nthr < nrec) {
-          const unsigned c01 = (unsigned)hc[r][1], c23 = (unsigned)hc[r][2];
-          nla[hc[r][0]] = vc[r][0] * l_alpha[c01 & 0xffffu] + vc[r][1] * l_alpha[c01 >> 16] +
-                          vc[r][2] * l_alpha[c23 & 0xffffu] + vc[r][3] * l_alpha[c23 >> 16];
-        }
+        const int dst = tid + r * nthr < nrec ? hc[r][0] : plane_pts + lane;
+        const unsigned c01 = (unsigned)hc[r][1], c23 = (unsigned)hc[r][2];
+        nla[dst] = vc[r][0] * l_alpha[c01 & 0xffffu] + vc[r][1] * l_alpha[c01 >> 16] +
+                   vc[r][2] * l_alpha[c23 & 0xffffu] + vc[r][3] * l_alpha[c23 >> 16];
       }
     }
     __syncthreads();
 
-    if (active) {
-      TC acc[PY];
+    TC acc[PY];
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+      TC t = a.c0 * TC(q[R][j]);
+#pragma unroll
+      for (int p = 1; p <= R; ++p) t += a.cz[p] * (TC(q[R + p][j]) + TC(q[R - p][j]));
+      acc[j] = t;
+    }
+    // y part: each LDS row of the column is read once and feeds every row it neighbours
+#pragma unroll
+    for (int t = 0; t < PY + 2 * R; ++t) {
+      const TC v = TC(tl[(ly0 + t) * pitch + R + x]);
 #pragma unroll
       for (int j = 0; j < PY; ++j) {
-        TC t = a.c0 * TC(q[R][j]);
-#pragma unroll
-        for (int p = 1; p <= R; ++p) t += a.cz[p] * (TC(q[R + p][j]) + TC(q[R - p][j]));
-        acc[j] = t;
+        const int p = t - R - j;
+        if (p != 0 && p >= -R && p <= R) acc[j] += a.cy[p < 0 ? -p : p] * v;
       }
-      // y part: each LDS row of the column is read once and feeds every row it neighbours
+    }
+    // x part: neighbours inside the row
 #pragma unroll
-      for (int t = 0; t < PY + 2 * R; ++t) {
-        const TC v = TC(tl[(ly0 + t) * pitch + R + x]);
+    for (int j = 0; j < PY; ++j) {
+      const TI* row = tl + (R + ly0 + j) * pitch + R + x;
+      TC t = TC(0);
 #pragma unroll
-        for (int j = 0; j < PY; ++j) {
-          const int p = t - R - j;
-          if (p != 0 && p >= -R && p <= R) acc[j] += a.cy[p < 0 ? -p : p] * v;
-        }
+      for (int p = 1; p <= R; ++p) t += a.cx[p] * (TC(row[p]) + TC(row[-p]));
+      acc[j] += t;
+    }
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+      const TC v = TC(q[R][j]);
+      TC hy = acc[j] + cv[j] * v;
+      if (NL) {
+        const int li = active ? (ly0 + j) * nx + x : plane_pts + lane;
+        hy += nla[li];
+        nla[li] = TC(0);
       }
-      // x part: neighbours inside the row
-#pragma unroll
-      for (int j = 0; j < PY; ++j) {
-        const TI* row = tl + (R + ly0 + j) * pitch + R + x;
-        TC t = TC(0);
-#pragma unroll
-        for (int p = 1; p <= R; ++p) t += a.cx[p] * (TC(row[p]) + TC(row[-p]));
-        acc[j] += t;
-      }
-#pragma unroll
-      for (int j = 0; j < PY; ++j) {
-        if (!valid[j]) continue;
-        const TC v = TC(q[R][j]);
-        TC hy = acc[j] + cv[j] * v;
-        if (NL) {
-          const int li = (ly0 + j) * nx + x;
-          hy += nla[li];
-          nla[li] = TC(0);
-        }
-        bstore<TO>(ro, TO(a.sa * (hy - a.sc * v) + a.sb * cp[j]), vp[j], (unsigned)(nplane * z) * (unsigned)sizeof(TO));
-      }
+      // idle lanes and rows past ny store through a kOOB offset: no write
+      bstore<TO>(ro, TO(a.sa * (hy - a.sc * v) + a.sb * cp[j]), vp[j], zo * (unsigned)sizeof(TO));
     }
     if (NL) {
 #pragma unroll
@@ -403,11 +434,11 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
 }
 
 size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes) {
-  size_t lds = 2 * (size_t)(p.ty + 2 * radius) * (nx + 2 * radius) * elem_bytes;
+  size_t lds = 2 * ((size_t)(p.ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes) + kHxDummy) * elem_bytes;
   if (np_tot >= 0) {
     lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
     lds += (size_t)((np_tot + 1) & ~1) * acc_bytes;
-    lds += 2 * (size_t)p.ty * nx * acc_bytes;
+    lds += 2 * ((size_t)p.ty * nx + kHxDummy) * acc_bytes;
   }
   return lds;
 }
@@ -423,18 +454,19 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   bool best_tall = false;
   const double big_block = elem_bytes == 8 ? 1.2 : 1.35;
   const double two_rows = elem_bytes == 8 ? 1.3 : 1.2;
-  const int pys[] = {1, 2, 3, 4};
+  const int pys[] = {1, 2};  // register queue budget (measured: three or four rows lose occupancy)
   for (int py : pys) {
     if (py_override > 0 && py != py_override) continue;
-    if (py_override <= 0 && py > 2) continue;  // register queue budget (measured: PY 3-4 lose occupancy)
     for (int nyg = 1; nx * nyg <= hx_max_threads(py); ++nyg) {
       if (nyg_override > 0 && nyg != nyg_override) continue;
       const int ty = nyg * py;
       const int nty = (ny + ty - 1) / ty;
       const int threads = nx * nyg;
       const int waves = (threads + 63) / 64;
-      if (2 * radius * nx > kHxMaxHalo * waves * 64) continue;  // halo values per thread bound
-      const size_t lds = 2 * (size_t)(ty + 2 * radius) * (nx + 2 * radius) * elem_bytes;
+      // staged values per thread bound (counted for a periodic x, the larger set)
+      const int nslots = hx_halo_slots(nx, ty, radius, 1);
+      if (nslots > kHxMaxHalo * waves * 64) continue;
+      const size_t lds = 2 * ((size_t)(ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes) + kHxDummy) * elem_bytes;
       if (lds > 48 * 1024) continue;
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
@@ -454,7 +486,7 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
         best.ty = ty;
         best.nty = nty;
         best.threads = waves * 64;
-        best.kh = (2 * radius * nx <= 2 * waves * 64) ? 2 : 4;
+        best.kh = std::max(2, (nslots + waves * 64 - 1) / (waves * 64));
         best.lds_tile_bytes = lds;
       }
     }
@@ -477,6 +509,7 @@ static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, in
   a.zc = p.zc;
   a.nzc = p.nzc;
   a.nblocks = (int64_t)p.nty * p.nzc * ns;
+  a.pitch = hx_pitch(a.nx, R, (int)sizeof(TI));
   a.per_xcd = (int)((a.nblocks + 7) / 8);
   const size_t lds = hx_lds_bytes(p, a.nx, R, (int)sizeof(TI), NL ? a.np_tot : -1, (int)sizeof(TC));
   if (lds > kHxMaxLds) return hipErrorInvalidConfiguration;
@@ -488,9 +521,16 @@ static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, in
 template <typename TI, typename TC, typename TO, int R, int PY>
 static hipError_t launch_rp(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int ns, hipStream_t s) {
   const bool nl = a.rec_ptr != nullptr;
-  if (p.kh <= 2)
-    return nl ? launch_final<TI, TC, TO, R, PY, 2, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 2, false>(a, p, ns, s);
-  return nl ? launch_final<TI, TC, TO, R, PY, 4, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 4, false>(a, p, ns, s);
+  switch (p.kh) {
+    case 2:
+      return nl ? launch_final<TI, TC, TO, R, PY, 2, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 2, false>(a, p, ns, s);
+    case 3:
+      return nl ? launch_final<TI, TC, TO, R, PY, 3, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 3, false>(a, p, ns, s);
+    case 4:
+      return nl ? launch_final<TI, TC, TO, R, PY, 4, true>(a, p, ns, s) : launch_final<TI, TC, TO, R, PY, 4, false>(a, p, ns, s);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename TI, typename TC, typename TO, int R>
@@ -498,8 +538,6 @@ static hipError_t launch_r(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int ns,
   switch (p.py) {
     case 1: return launch_rp<TI, TC, TO, R, 1>(a, p, ns, s);
     case 2: return launch_rp<TI, TC, TO, R, 2>(a, p, ns, s);
-    case 3: return launch_rp<TI, TC, TO, R, 3>(a, p, ns, s);
-    case 4: return launch_rp<TI, TC, TO, R, 4>(a, p, ns, s);
     default: return hipErrorInvalidValue;
   }
 }

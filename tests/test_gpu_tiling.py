@@ -20,9 +20,10 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# (rows per thread, row groups): with nx = 40 and r = 6 these give KH = 2 and KH = 4 for
-# both PY = 1 and PY = 2 (KH = 4 when 2 r nx > 2 x the block's lanes)
-TILINGS = [(1, 3), (1, 8), (1, 24), (2, 4), (2, 6), (2, 12), (3, 3), (4, 2)]
+# (rows per thread, row groups): with nx = 40 and r = 6 these give KH = 4, 3 and 2 staged
+# values per thread for both PY = 1 and PY = 2 (the staged set of a tile of ty rows is
+# 2r (nx + 2r) halo-row values plus 2r ty periodic x copies, spread over the block's lanes)
+TILINGS = [(1, 4), (1, 8), (1, 24), (2, 4), (2, 6), (2, 12)]
 GRIDS = [((40, 24, 16), (0, 0, 0)), ((40, 23, 18), (0, 1, 1))]
 
 
@@ -66,14 +67,14 @@ def test_apply_h_every_tiling(cs, grid, prec):
         assert np.abs(got - ref).max() <= tol
         seen.add((t[0], t[3]))
         outs.append(got)
-    assert {(1, 2), (1, 4), (2, 2), (2, 4)} <= seen
+    assert {(1, 2), (1, 3), (1, 4), (2, 2), (2, 3), (2, 4)} <= seen
     for o in outs[1:]:
         assert np.abs(o - outs[0]).max() <= (1e-13 if prec == "fp64" else 1e-6) * scale
     h.chefsi_set_stencil_tiling(0, 0)
     assert h.chefsi_get_stencil_tiling() == default
 
 
-@pytest.mark.parametrize("tiling", [(1, 3), (2, 4), (2, 12)])
+@pytest.mark.parametrize("tiling", [(1, 4), (1, 8), (2, 4), (2, 12)])
 def test_refine_degree0_every_tiling(cs, tiling):
     """The refinement's H X in FP64 from an FP32 block (the <float, double, double> pass)."""
     prob = inputs.small_problem(n=(40, 24, 16), bc=(0, 0, 1), n_atoms=5, nproj_per_atom=4, seed=13)
@@ -90,7 +91,7 @@ def test_refine_degree0_every_tiling(cs, tiling):
 
 def test_mixed_solve_with_two_rows_and_four_halo_values(cs):
     """A whole mixed solve (mixed steps + FP64 refinement) in the tiling the 120^3 FP32
-    workload runs (two rows per thread, four halo values per thread) against the oracle."""
+    workload runs (two rows per thread, four staged values per thread) against the oracle."""
     prob = inputs.small_problem(n=(40, 24, 16), bc=(0, 0, 1), n_atoms=5, nproj_per_atom=4, seed=13)
     ns, degree, n_iter = 24, 12, 5
     x0 = inputs.initial_block(prob.nd, ns, 77).T
@@ -107,3 +108,57 @@ def test_mixed_solve_with_two_rows_and_four_halo_values(cs):
     rho = oc.subspace_residual(x_ref, host(Xd), k)
     print(f"PY=2 KH=4 mixed solve: N_chk={k} max|dRitz|={err:.2e} rho={rho:.2e}", flush=True)
     assert err <= 1e-5 and rho <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_projector_terms_in_the_scatter_pass(cs, prec):
+    """Every projector term in the separate scatter pass (no stencil-pass records) against
+    the oracle, with overlapping supports, and back to the default split."""
+    prob = inputs.small_problem(n=(30, 26, 22), h=(0.3, 0.3, 0.3), bc=(0, 0, 1), fd_order=12, n_atoms=9,
+                                nproj_per_atom=4, seed=23)
+    ns = 6
+    dt = "float64" if prec == "fp64" else "float32"
+    X = np.random.default_rng(8).standard_normal((prob.nd, ns)).astype(dt)
+    ref = apply_h(prob, X.astype(np.float64))
+    scale = stencil_scale(prob) * np.abs(X).max()
+    tol = 1e-12 * scale if prec == "fp64" else 2e-6 * scale
+    h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+    outs = []
+    for in_stencil in (False, True, False):
+        h.chefsi_set_projector_pass(in_stencil)
+        Yd = torch.zeros(ns, prob.nd, dtype=getattr(torch, dt), device="cuda")
+        h.chefsi_apply_h(dev(X, dt), Yd, ns, ws)
+        torch.cuda.synchronize()
+        got = host(Yd)
+        assert np.abs(got - ref).max() <= tol
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[2])
+    assert np.abs(outs[0] - outs[1]).max() <= (1e-13 if prec == "fp64" else 1e-6) * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_keeps_x_and_parity(cs, prec):
+    """chefsi_autotune times the candidate tilings and projector splits on the caller's
+    block without changing it; H X in the chosen configuration matches the oracle."""
+    prob = inputs.small_problem(n=(40, 23, 18), h=(0.3, 0.27, 0.33), bc=(0, 1, 1), fd_order=12, n_atoms=6,
+                                nproj_per_atom=4, seed=81)
+    ns = 7
+    dt = "float64" if prec == "fp64" else "float32"
+    X = np.random.default_rng(9).standard_normal((prob.nd, ns)).astype(dt)
+    ref = apply_h(prob, X.astype(np.float64))
+    scale = stencil_scale(prob) * np.abs(X).max()
+    tol = 1e-12 * scale if prec == "fp64" else 2e-6 * scale
+    h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+    Xd = dev(X, dt)
+    py, nyg, in_stencil = h.chefsi_autotune(Xd, ns, ws)
+    torch.cuda.synchronize()
+    print(f"{prec}: autotune chose PY={py} groups={nyg} in_stencil={in_stencil}", flush=True)
+    assert np.array_equal(host(Xd), X.astype(np.float64))
+    t = h.chefsi_get_stencil_tiling()
+    assert (t[0], t[1]) == (py, nyg)
+    Yd = torch.zeros_like(Xd)
+    h.chefsi_apply_h(Xd, Yd, ns, ws)
+    torch.cuda.synchronize()
+    assert np.abs(host(Yd) - ref).max() <= tol
