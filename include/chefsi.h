@@ -151,16 +151,20 @@ int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32
 /* Where the projector term of H X is added (Sec. 2.1, third bullet; results agree to
  * rounding).  in_stencil = 1 (default): points inside at most four projector entries
  * take it inside the stencil pass from per-point records, the others in a separate
- * scatter pass; in_stencil = 0: every touched point takes it in the scatter pass (one
- * thread per point and eight orbitals, the point's entries read once per eight
- * orbitals), and the stencil pass runs without records.  Rebuilds the handle's tables;
- * for tuning and tests, not while calls on the handle are in flight. */
+ * scatter pass, after a gather of the coefficients over each atom's support.
+ * in_stencil = 0 (band pass): the stencil pass runs without records, and one pass over
+ * the touched points, region by region (a z plane x a band of rows), adds every
+ * projector term and forms, from the finished values, fixed-order partial sums of the
+ * next application's coefficients (the filter carries them from one application to the
+ * next).  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
+ * orbitals on the device); for tuning and tests, not while calls on the handle are in
+ * flight. */
 int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
 
 /* Picks the stencil tiling and the projector split by timing them (the planner's
  * tilings of at least r + 1 rows, each with the projector term in the stencil pass for
  * points inside at most four entries and with every term in the scatter pass): three
- * filter-form H applications per candidate on the first min(ns, 256) orbitals of the
+ * filter-form H applications per candidate on the first min(ns, 1024) orbitals of the
  * device block X (read only; the workspace block takes the results), on `stream`, which
  * the call synchronises.  Keeps the fastest and, when choice is not NULL, writes
  * {rows per thread, row groups, in_stencil} to choice[0..2].  Results after tuning agree

@@ -161,8 +161,27 @@ struct chefsi_handle {
   size_t hx_rec_bytes = 0;   // device bytes of the stencil-pass records
   size_t scatter_bytes = 0;  // device bytes of the scatter records and entries
   // points in at most this many projector entries take their projector term inside the
-  // stencil pass (4: the record width); the others go to the scatter pass (0: all)
+  // stencil pass (4: the record width), the others in the scatter pass; 0: every term in
+  // the band pass (nl_band) instead
   int rec_max = 4;
+  // band-pass tables (built while rec_max == 0)
+  int nb_reg = 0, nb_pts = 0, nb_slots = 0;
+  int* nb_reg_pt = nullptr;
+  int* nb_pt_idx = nullptr;
+  int* nb_pt_ent = nullptr;
+  int* nb_ent_ls = nullptr;
+  int* nb_slot_q = nullptr;
+  double* nb_ent_chi64 = nullptr;
+  float* nb_ent_chi32 = nullptr;
+  int* nb_reg_slot = nullptr;
+  int* nb_slot_ent = nullptr;
+  int* nb_gent_loc = nullptr;
+  double* nb_gent_chi64 = nullptr;
+  float* nb_gent_chi32 = nullptr;
+  int* nb_q_slot_ptr = nullptr;
+  int* nb_q_slot = nullptr;
+  void* nb_partial = nullptr;  // nb_slots x max_ns values (8 bytes each)
+  size_t nb_bytes = 0;
 
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -517,9 +536,55 @@ NlArgs<TI, TC> nl_args(const chefsi_handle* h, const TI* y, int ns, const TC* ch
 // out = sa (H x - sc x) + sb prev, with the projector gather for x first.
 // out = sa ((H x) - sc x) + sb prev: projector gather (alpha), the stencil + Veff +
 // Chebyshev pass, then the projector scatter onto the support points.
+// Band-pass arguments for block y (the handle's tables for compute type TC).
+template <typename TY, typename TC>
+NbArgs<TY, TC> band_args(const chefsi_handle* h, TY* y, int ns, const TC* alpha, double sa) {
+  NbArgs<TY, TC> a{};
+  a.y = y;
+  a.nd = h->nd;
+  a.ns = ns;
+  a.nreg = h->nb_reg;
+  a.reg_pt = h->nb_reg_pt;
+  a.pt_idx = h->nb_pt_idx;
+  a.pt_ent = h->nb_pt_ent;
+  a.ent_ls = h->nb_ent_ls;
+  a.slot_q = h->nb_slot_q;
+  a.reg_slot = h->nb_reg_slot;
+  a.slot_ent = h->nb_slot_ent;
+  a.gent_loc = h->nb_gent_loc;
+  if constexpr (sizeof(TC) == 8) {
+    a.ent_chi = h->nb_ent_chi64;
+    a.gent_chi = h->nb_gent_chi64;
+  } else {
+    a.ent_chi = h->nb_ent_chi32;
+    a.gent_chi = h->nb_gent_chi32;
+  }
+  a.alpha = alpha;
+  a.sa = TC(sa);
+  a.partial = static_cast<TC*>(h->nb_partial);
+  return a;
+}
+
+// alpha (projector-major) of block y from the band pass's slot partials
+template <typename TY, typename TC>
+void band_alpha(chefsi_handle* h, TY* y, int ns, TC* alpha, const TC* gdv, bool scatter, double sa,
+                bool want_alpha, hipStream_t s) {
+  ProfScope ps(h, P_NL, s);
+  HIP_TRY((launch_nl_band<TY, TC>(band_args<TY, TC>(h, y, ns, alpha, sa), scatter, want_alpha, s)));
+  if (want_alpha)
+    HIP_TRY(launch_nl_band_reduce<TC>(static_cast<const TC*>(h->nb_partial), h->nb_q_slot_ptr, h->nb_q_slot, gdv,
+                                      h->np_tot, ns, alpha, s));
+  ps.done();
+}
+
+// out = sa ((H - sc) x) + sb prev.  The projector term takes one of two routes: stencil-pass
+// records plus a scatter pass for the points in more than four entries (the gather nl_project
+// first), or, on a handle switched to the band pass, nl_band after a bare stencil pass.  In
+// the band route alpha holds projector-major coefficients: alpha_ready says they are already
+// those of x (the previous application computed them), want_next asks for those of out.
 template <typename TI, typename TC, typename TO>
 void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns, double sa, double sc, double sb,
-                 TC* alpha, hipStream_t s) {
+                 TC* alpha, hipStream_t s, bool alpha_ready = false, bool want_next = false) {
   const TC* veff;
   const TC* nlv;
   const TC* chi;
@@ -535,7 +600,10 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
     chi = h->chi32;
     gdv = h->gdv32;
   }
-  if (h->np_tot > 0) {
+  const bool band = h->np_tot > 0 && h->rec_max == 0;
+  if (band) {
+    if (!alpha_ready) band_alpha<TI, TC>(h, const_cast<TI*>(x), ns, alpha, gdv, false, 0.0, true, s);
+  } else if (h->np_tot > 0) {
     ProfScope ps(h, P_NL, s);
     HIP_TRY((launch_nl_project<TI, TC>(nl_args<TI, TC>(h, x, ns, chi, gdv, alpha), s)));
     ps.done();
@@ -552,7 +620,9 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
     HIP_TRY((launch_hx<TI, TC, TO>(a, p, h->radius, ns, s)));
     ps.done();
   }
-  if (h->n_pts > 0) {
+  if (band) {
+    band_alpha<TO, TC>(h, out, ns, alpha, gdv, true, sa, want_next, s);
+  } else if (h->n_pts > 0) {
     NsArgs<TC, TO> n{};
     n.out = out;
     n.nd = h->nd;
@@ -572,20 +642,22 @@ void apply_fused(chefsi_handle* h, const TI* x, const TO* prev, TO* out, int ns,
 
 // Scaled Chebyshev filter (Alg. 1, Filtering).  Y_0 = X in buffer A; Y_{k+1} overwrites Y_{k-1}.
 // Returns the buffer that holds Y_m (A when m is even, B when odd).
+// With carry_last, alpha ends as the band-pass coefficients of the returned block.
 template <typename T>
 T* run_filter(chefsi_handle* h, T* A, T* B, int ns, int m, double lo, double cut, double hi, T* alpha,
-              hipStream_t s) {
+              hipStream_t s, bool carry_last = false) {
   const double c = 0.5 * (hi + cut);
   const double e = 0.5 * (hi - cut);
   const double s1 = e / (lo - c);
   double sig = s1;
   // Y_1 = (s1 / e)(H - c) Y_0
-  apply_fused<T, T, T>(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s);
+  apply_fused<T, T, T>(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s, false, m > 1 || carry_last);
   T* cur = B;
   T* other = A;
   for (int k = 1; k < m; ++k) {
     const double sig_next = 1.0 / (2.0 / s1 - sig);
-    apply_fused<T, T, T>(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s);
+    apply_fused<T, T, T>(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s, true,
+                         k + 1 < m || carry_last);
     std::swap(cur, other);
     sig = sig_next;
   }
@@ -904,9 +976,9 @@ void step_impl(chefsi_handle* h, T* X, int ns, int m, double lo, double cut, dou
   double* Hs = at<double>(ws, L.hs);
   double* Ms = at<double>(ws, L.ms);
   double* D = at<double>(ws, L.d);
-  T* Xf = run_filter<T>(h, A, B, ns, m, lo, cut, hi, alpha, s);
+  T* Xf = run_filter<T>(h, A, B, ns, m, lo, cut, hi, alpha, s, true);
   T* Yf = Xf == A ? B : A;
-  apply_fused<T, T, T>(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
+  apply_fused<T, T, T>(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s, true);  // Y~ = H X~
   Gemm g = step_gemm(h);
   gram_pair<T, T>(h, Xf, Yf, ns, L, ws, Hs, Ms, s, g);
   dense_factor(h, Hs, Ms, ns, L, ws, s);
@@ -1065,16 +1137,149 @@ void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
   h->hx_plan = hp;
 }
 
+void free_band_tables(chefsi_handle* h) {
+  void* ptrs[] = {h->nb_reg_pt,   h->nb_pt_idx,     h->nb_pt_ent,     h->nb_ent_ls,   h->nb_ent_chi64,
+                  h->nb_ent_chi32, h->nb_reg_slot,  h->nb_slot_ent,   h->nb_gent_loc, h->nb_gent_chi64,
+                  h->nb_gent_chi32, h->nb_q_slot_ptr, h->nb_q_slot,   h->nb_partial, h->nb_slot_q};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  h->nb_reg_pt = h->nb_pt_idx = h->nb_pt_ent = h->nb_ent_ls = h->nb_slot_q = nullptr;
+  h->nb_reg_slot = h->nb_slot_ent = h->nb_gent_loc = h->nb_q_slot_ptr = h->nb_q_slot = nullptr;
+  h->nb_ent_chi64 = h->nb_gent_chi64 = nullptr;
+  h->nb_ent_chi32 = h->nb_gent_chi32 = nullptr;
+  h->nb_partial = nullptr;
+  h->device_bytes -= h->nb_bytes;
+  h->nb_bytes = 0;
+  h->nb_reg = h->nb_pts = h->nb_slots = 0;
+}
+
+// Band-pass tables from the point-major projector table: regions of one z plane x a band of
+// rows, the band height the largest with at most kBandMaxPts touched points per region;
+// each region lists its touched points (index order) with their entries, and its projector
+// slots (projector order) with their entries (point order); each projector lists its slots
+// (region order) for the reduction.
+void build_band_tables(chefsi_handle* h) {
+  free_band_tables(h);
+  const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+  const std::vector<int>& cnt = h->pt_cnt;
+  std::vector<int> row_pts((size_t)ny * nz, 0);
+  for (int64_t i = 0; i < h->nd; ++i)
+    if (cnt[i + 1] > cnt[i]) row_pts[i / nx] += 1;
+  // projectors touching each row (for the slot bound)
+  std::vector<std::vector<int>> row_q((size_t)ny * nz);
+  for (int64_t i = 0; i < h->nd; ++i)
+    for (int e = cnt[i]; e < cnt[i + 1]; ++e) row_q[i / nx].push_back(h->pt_col[e]);
+  for (auto& v : row_q) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  auto fits = [&](int hb) {
+    for (int z = 0; z < nz; ++z)
+      for (int y0 = 0; y0 < ny; y0 += hb) {
+        int c = 0;
+        std::vector<int> qs;
+        for (int y = y0; y < std::min(ny, y0 + hb); ++y) {
+          c += row_pts[(size_t)z * ny + y];
+          qs.insert(qs.end(), row_q[(size_t)z * ny + y].begin(), row_q[(size_t)z * ny + y].end());
+        }
+        std::sort(qs.begin(), qs.end());
+        qs.erase(std::unique(qs.begin(), qs.end()), qs.end());
+        if (c > kBandMaxPts || (int)qs.size() > kBandMaxSlots) return false;
+      }
+    return true;
+  };
+  check(fits(1), "a grid row holds too many touched points or projectors for the band pass");
+  int hb = 1;
+  while (hb < ny && fits(hb + 1)) ++hb;
+  const int nbands = (ny + hb - 1) / hb;
+  std::vector<int> reg_pt(1, 0), pt_idx, pt_ent(1, 0), ent_q, ent_ls, reg_slot(1, 0), slot_ent(1, 0), gent_loc,
+      slot_q;
+  std::vector<double> ent_chi, gent_chi;
+  std::vector<std::vector<int>> q_slots(h->np_tot);
+  for (int z = 0; z < nz; ++z)
+    for (int b = 0; b < nbands; ++b) {
+      const int first = (int)pt_idx.size();
+      std::map<int, std::vector<std::pair<int, double>>> slots;  // projector -> (local point, chi)
+      for (int y = b * hb; y < std::min(ny, (b + 1) * hb); ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t i = x + (int64_t)nx * (y + (int64_t)ny * z);
+          if (cnt[i + 1] == cnt[i]) continue;
+          const int loc = (int)pt_idx.size() - first;
+          pt_idx.push_back((int)i);
+          for (int e = cnt[i]; e < cnt[i + 1]; ++e) {
+            ent_q.push_back(h->pt_col[e]);
+            ent_chi.push_back(h->pt_val[e]);
+            slots[h->pt_col[e]].emplace_back(loc, h->pt_val[e]);
+          }
+          pt_ent.push_back((int)ent_q.size());
+        }
+      reg_pt.push_back((int)pt_idx.size());
+      // region slot of every entry of the region's points (slots in projector order)
+      std::map<int, int> local;
+      for (auto& kv : slots) local.emplace(kv.first, (int)local.size());
+      for (size_t e = ent_ls.size(); e < ent_q.size(); ++e) ent_ls.push_back(local.at(ent_q[e]));
+      for (auto& kv : slots) {
+        q_slots[kv.first].push_back((int)slot_q.size());
+        slot_q.push_back(kv.first);
+        for (auto& pe : kv.second) {
+          gent_loc.push_back(pe.first);
+          gent_chi.push_back(pe.second);
+        }
+        slot_ent.push_back((int)gent_loc.size());
+      }
+      reg_slot.push_back((int)slot_q.size());
+    }
+  std::vector<int> q_slot_ptr(1, 0), q_slot;
+  for (int q = 0; q < h->np_tot; ++q) {
+    for (int sl : q_slots[q]) q_slot.push_back(sl);
+    q_slot_ptr.push_back((int)q_slot.size());
+  }
+  const size_t before = h->device_bytes;
+  try {
+    h->nb_reg_pt = upload(h, reg_pt.data(), reg_pt.size());
+    h->nb_pt_idx = upload(h, pt_idx.data(), pt_idx.size());
+    h->nb_pt_ent = upload(h, pt_ent.data(), pt_ent.size());
+    h->nb_ent_ls = upload(h, ent_ls.data(), ent_ls.size());
+    h->nb_slot_q = upload(h, slot_q.data(), slot_q.size());
+    h->nb_ent_chi64 = upload(h, ent_chi.data(), ent_chi.size());
+    std::vector<float> f(ent_chi.begin(), ent_chi.end());
+    h->nb_ent_chi32 = upload(h, f.data(), f.size());
+    h->nb_reg_slot = upload(h, reg_slot.data(), reg_slot.size());
+    h->nb_slot_ent = upload(h, slot_ent.data(), slot_ent.size());
+    h->nb_gent_loc = upload(h, gent_loc.data(), gent_loc.size());
+    h->nb_gent_chi64 = upload(h, gent_chi.data(), gent_chi.size());
+    std::vector<float> g(gent_chi.begin(), gent_chi.end());
+    h->nb_gent_chi32 = upload(h, g.data(), g.size());
+    h->nb_q_slot_ptr = upload(h, q_slot_ptr.data(), q_slot_ptr.size());
+    h->nb_q_slot = upload(h, q_slot.data(), q_slot.size());
+    const size_t pbytes = std::max<size_t>(1, slot_q.size()) * (size_t)h->max_ns * 8;
+    if (hipMalloc(&h->nb_partial, pbytes) != hipSuccess) {
+      h->nb_partial = nullptr;
+      throw Error{CHEFSI_ERR_OOM, "device allocation failed (band-pass partial sums)"};
+    }
+    h->device_bytes += pbytes;
+  } catch (...) {
+    h->nb_bytes = h->device_bytes - before;
+    free_band_tables(h);
+    throw;
+  }
+  h->nb_bytes = h->device_bytes - before;
+  h->nb_reg = (int)reg_pt.size() - 1;
+  h->nb_pts = (int)pt_idx.size();
+  h->nb_slots = (int)slot_q.size();
+}
+
 // Scatter-pass records for the points in more than rec_max projector entries (all touched
 // points when rec_max is 0): one record {point, first entry, entry count, 0} each, entries
 // in atom order padded with zeros to a multiple of 4; replaces the handle's current ones.
 void build_scatter_records(chefsi_handle* h) {
   std::vector<int4> recs;
+  const bool band = h->rec_max == 0;  // the band pass takes every term: no scatter records
   std::vector<int> ecol;
   std::vector<double> evals;
   for (int64_t i = 0; i < h->nd; ++i) {
     const int b = h->pt_cnt[i], n = h->pt_cnt[i + 1] - b;
-    if (n <= h->rec_max) continue;
+    if (band || n <= h->rec_max) continue;
     recs.push_back(make_int4((int)i, (int)ecol.size(), n, 0));
     for (int k = b; k < b + n; ++k) {
       ecol.push_back(h->pt_col[k]);
@@ -1117,6 +1322,7 @@ void build_scatter_records(chefsi_handle* h) {
 }
 
 void release(chefsi_handle* h) {
+  free_band_tables(h);
   void* ptrs[] = {h->veff64, h->veff32, h->supp_off, h->supp_idx, h->chi_off,  h->nproj,    h->poff,
                   h->chi64,  h->chi32,  h->gdv64,    h->gdv32,    h->rec,      h->ent_col,  h->hx_rec_ptr,
                   h->hx_rec64, h->hx_rec32,
@@ -2070,9 +2276,9 @@ template <typename T>
 static float time_filter_launch(chefsi_handle* h, const T* X, T* B, int ns, T* alpha, hipStream_t s,
                                 hipEvent_t e0, hipEvent_t e1) {
   constexpr int kWarm = 1, kRuns = 3;
-  for (int i = 0; i < kWarm; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s);
+  for (int i = 0; i < kWarm; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s, false, true);
   HIP_TRY(hipEventRecord(e0, s));
-  for (int i = 0; i < kRuns; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s);
+  for (int i = 0; i < kRuns; ++i) apply_fused<T, T, T>(h, X, B, B, ns, 0.5, 0.25, -0.5, alpha, s, true, true);
   HIP_TRY(hipEventRecord(e1, s));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -2089,7 +2295,7 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
     WsLayout L;
     check_ws(h, ns, ws, ws_bytes, L);
     hipStream_t s = (hipStream_t)stream;
-    const int nt = std::min(ns, 256);  // orbitals timed: the per-orbital work is the same for all
+    const int nt = std::min(ns, 1024);  // orbitals timed: the per-orbital work is the same for all
     const int eb = h->precision == CHEFSI_FP64 ? 8 : 4;
     const int nx = h->n[0], ny = h->n[1];
     // candidate tilings: every row count per thread and row-group count the planner accepts,
@@ -2122,6 +2328,10 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
       if (h->rec_max != mode) {
         h->rec_max = mode;
         build_scatter_records(h);
+        if (mode == 0)
+          build_band_tables(h);
+        else
+          free_band_tables(h);
       }
       for (size_t c = 0; c < cands.size(); ++c) {
         if (h->np_tot > 0)
@@ -2146,6 +2356,10 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
     if (h->rec_max != best_mode) {
       h->rec_max = best_mode;
       build_scatter_records(h);
+      if (best_mode == 0)
+        build_band_tables(h);
+      else
+        free_band_tables(h);
     }
     if (h->np_tot > 0)
       build_hx_records(h, cands[best_c]);
@@ -2170,6 +2384,10 @@ int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil) {
     h->rec_max = want;
     build_hx_records(h, h->hx_plan);
     build_scatter_records(h);
+    if (want == 0)
+      build_band_tables(h);
+    else
+      free_band_tables(h);
   });
 }
 

@@ -144,6 +144,49 @@ template <typename TC, typename TO>
 hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// nl_band: the whole projector term of H y in one pass over the touched points, region by
+// region (a region = one z plane x a band of rows; its touched points in index order).
+// A block owns one region and G orbitals:
+//   scatter (optional): y[v][i] += sa * sum_{e in entries(i)} chi_e * alpha[q_e][v], written
+//   in place (alpha projector-major: alpha[q * ns + v]);
+//   gather: for every projector q touching the region (a slot), partial[slot][v] =
+//   sum over the region's points of q, in index order, of chi * y[v][i] (the final y);
+// and nl_band_reduce forms alpha[q][v] = gdv[q] * sum of q's slots in region order.  Every
+// sum has a fixed order: the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kBandMaxPts = 512;    // touched points of one region (LDS: kBandMaxPts * G values)
+constexpr int kBandMaxSlots = 256;  // projectors touching one region (their coefficients staged in LDS)
+
+template <typename TY, typename TC>
+struct NbArgs {
+  TY* y;               // Nd x ns block (ld nd): scattered in place when scatter, read otherwise
+  int64_t nd;
+  int ns;
+  int nreg;
+  const int* reg_pt;   // nreg + 1: points of region r are [reg_pt[r], reg_pt[r + 1])
+  const int* pt_idx;   // grid index of each point
+  const int* pt_ent;   // npts + 1: entries of point p
+  const int* ent_ls;   // region slot of each entry (the projector's place among the region's slots)
+  const TC* ent_chi;
+  const int* reg_slot;  // nreg + 1: slots of region r
+  const int* slot_q;    // projector column of each slot
+  const int* slot_ent;  // nslots + 1: gather entries of slot s
+  const int* gent_loc;  // point of each gather entry, relative to its region's first point
+  const TC* gent_chi;
+  const TC* alpha;      // scatter: projector-major coefficients (the region's staged in LDS)
+  TC sa;
+  TC* partial;          // nslots x ns, projector slot major
+  int ngroups;          // orbital groups (set by the launcher)
+  int per_xcd;          // blocks per XCD (set by the launcher)
+};
+
+template <typename TY, typename TC>
+hipError_t launch_nl_band(const NbArgs<TY, TC>& a, bool scatter, bool gather, hipStream_t s);
+template <typename TC>
+hipError_t launch_nl_band_reduce(const TC* partial, const int* q_slot_ptr, const int* q_slot, const TC* gdv,
+                                 int np_tot, int ns, TC* alpha, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Dense products on MFMA.
 // gram:   partial[split][tile] = A(:, I)^T B(:, J) over a K range, for upper tiles I <= J.
 // reduce: C(i, j) = C(j, i) = sum_split partial (i <= j), C is ns x ns, ld ns, FP64.

@@ -145,6 +145,136 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Orbitals per band block: the region's final values of G orbitals sit in LDS
+// (kBandMaxPts * G * sizeof(TC) = 64 KB).
+template <typename TC>
+constexpr int band_g() { return sizeof(TC) == 8 ? 4 : 8; }
+
+// Blocks are dealt to the 8 XCDs in turn and each XCD takes a contiguous run of logical
+// ids, region-major with the orbital group fastest: the blocks resident on an XCD share one
+// region's tables (point entries, slot entries) through its L2 while they sweep orbitals.
+template <typename TY, typename TC, bool SCATTER>
+__global__ __launch_bounds__(256) void nl_band_kernel(NbArgs<TY, TC> a, int gather) {
+  constexpr int G = band_g<TC>();
+  __shared__ TC ys[kBandMaxPts * G];
+  __shared__ TC as[kBandMaxSlots * G];
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+  if (logical >= (int64_t)a.nreg * a.ngroups) return;
+  const int reg = (int)(logical / a.ngroups);
+  const int v0 = (int)(logical % a.ngroups) * G;
+  const int nv = min(G, a.ns - v0);
+  const int p0 = a.reg_pt[reg], np = a.reg_pt[reg + 1] - p0;
+  const int s0 = a.reg_slot[reg], nslot = a.reg_slot[reg + 1] - s0;
+  if (SCATTER) {  // the coefficients of the region's projectors for the block's orbitals
+    for (int it = threadIdx.x; it < nslot * G; it += 256) {
+      const int ls = it / G, u = it % G;
+      as[it] = u < nv ? a.alpha[(int64_t)a.slot_q[s0 + ls] * a.ns + v0 + u] : TC(0);
+    }
+    __syncthreads();
+  }
+  // the region's points: final values (after the scatter) to LDS
+  for (int p = threadIdx.x; p < np; p += 256) {
+    const int64_t i = a.pt_idx[p0 + p];
+    TC y[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) y[u] = u < nv ? TC(a.y[(int64_t)(v0 + u) * a.nd + i]) : TC(0);
+    if (SCATTER) {
+      TC t[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) t[u] = TC(0);
+      const int e0 = a.pt_ent[p0 + p], e1 = a.pt_ent[p0 + p + 1];
+      for (int e = e0; e < e1; ++e) {
+        const TC c = a.ent_chi[e];
+        const TC* al = as + a.ent_ls[e] * G;
+#pragma unroll
+        for (int u = 0; u < G; ++u) t[u] += c * al[u];
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (u >= nv) break;
+        y[u] += a.sa * t[u];
+        a.y[(int64_t)(v0 + u) * a.nd + i] = TY(y[u]);
+        y[u] = TC(TY(y[u]));  // the gather reads the stored value
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) ys[p * G + u] = y[u];
+  }
+  if (!gather) return;
+  __syncthreads();
+  // slot partials: one thread per (slot, orbital), the slot's entries summed in index order
+  // (entries fetched eight at a time so their loads overlap)
+  for (int it = threadIdx.x; it < nslot * G; it += 256) {
+    const int sl = s0 + it / G, u = it % G;
+    if (u >= nv) continue;
+    TC sum = TC(0);
+    int e = a.slot_ent[sl];
+    const int e1 = a.slot_ent[sl + 1];
+    for (; e + 8 <= e1; e += 8) {
+      int l[8];
+      TC c[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        l[k] = a.gent_loc[e + k];
+        c[k] = a.gent_chi[e + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sum += c[k] * ys[l[k] * G + u];
+    }
+    for (; e < e1; ++e) sum += a.gent_chi[e] * ys[a.gent_loc[e] * G + u];
+    a.partial[(int64_t)sl * a.ns + v0 + u] = sum;
+  }
+}
+
+template <typename TY, typename TC>
+hipError_t launch_nl_band(const NbArgs<TY, TC>& a0, bool scatter, bool gather, hipStream_t s) {
+  if (a0.nreg <= 0 || a0.ns <= 0) return hipSuccess;
+  NbArgs<TY, TC> a = a0;
+  constexpr int G = band_g<TC>();
+  a.ngroups = (a.ns + G - 1) / G;
+  const int64_t nb = (int64_t)a.nreg * a.ngroups;
+  a.per_xcd = (int)((nb + 7) / 8);
+  const dim3 grid((unsigned)(a.per_xcd * 8));
+  if (scatter)
+    hipLaunchKernelGGL((nl_band_kernel<TY, TC, true>), grid, dim3(256), 0, s, a, gather ? 1 : 0);
+  else
+    hipLaunchKernelGGL((nl_band_kernel<TY, TC, false>), grid, dim3(256), 0, s, a, 1);
+  return hipGetLastError();
+}
+
+// alpha[q][v] = gdv[q] * sum over the slots of q (region order) of partial[slot][v].
+template <typename TC>
+__global__ __launch_bounds__(256) void nl_band_reduce_kernel(const TC* __restrict__ partial,
+                                                             const int* __restrict__ q_slot_ptr,
+                                                             const int* __restrict__ q_slot,
+                                                             const TC* __restrict__ gdv, int np_tot, int ns,
+                                                             TC* __restrict__ alpha) {
+  const int q = blockIdx.y;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (q >= np_tot || v >= ns) return;
+  TC sum = TC(0);
+  for (int k = q_slot_ptr[q]; k < q_slot_ptr[q + 1]; ++k) sum += partial[(int64_t)q_slot[k] * ns + v];
+  alpha[(int64_t)q * ns + v] = gdv[q] * sum;
+}
+
+template <typename TC>
+hipError_t launch_nl_band_reduce(const TC* partial, const int* q_slot_ptr, const int* q_slot, const TC* gdv,
+                                 int np_tot, int ns, TC* alpha, hipStream_t s) {
+  if (np_tot <= 0 || ns <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((ns + 255) / 256), (unsigned)np_tot);
+  hipLaunchKernelGGL(nl_band_reduce_kernel<TC>, grid, dim3(256), 0, s, partial, q_slot_ptr, q_slot, gdv, np_tot, ns,
+                     alpha);
+  return hipGetLastError();
+}
+
+template hipError_t launch_nl_band<double, double>(const NbArgs<double, double>&, bool, bool, hipStream_t);
+template hipError_t launch_nl_band<float, float>(const NbArgs<float, float>&, bool, bool, hipStream_t);
+template hipError_t launch_nl_band<float, double>(const NbArgs<float, double>&, bool, bool, hipStream_t);
+template hipError_t launch_nl_band_reduce<double>(const double*, const int*, const int*, const double*, int, int,
+                                                  double*, hipStream_t);
+template hipError_t launch_nl_band_reduce<float>(const float*, const int*, const int*, const float*, int, int,
+                                                 float*, hipStream_t);
+
 template hipError_t launch_nl_scatter<double, double>(const NsArgs<double, double>&, hipStream_t);
 template hipError_t launch_nl_scatter<float, float>(const NsArgs<float, float>&, hipStream_t);
 

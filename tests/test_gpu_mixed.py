@@ -46,7 +46,10 @@ def _f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("shape,ns", [((30, 31, 29), 137), ((9, 7, 6), 3), ((16, 16, 16), 128)])
+# ns >= 768 runs the 256-wide tile kernel: 800 (7 tiles of 128, the last 256-wide tile half
+# used) and 1031 (9 tiles of 128, a ragged last tile)
+@pytest.mark.parametrize("shape,ns", [((30, 31, 29), 137), ((9, 7, 6), 3), ((16, 16, 16), 128), ((30, 31, 29), 800),
+                                      ((28, 27, 26), 1031)])
 def test_project_split_bf16(cs, shape, ns):
     """Hs = X^T H X and Ms = X^T X from an FP32 block: split-bf16 bound, element by element."""
     from oracle.hamiltonian import apply_h

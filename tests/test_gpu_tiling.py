@@ -162,3 +162,40 @@ def test_autotune_keeps_x_and_parity(cs, prec):
     h.chefsi_apply_h(Xd, Yd, ns, ws)
     torch.cuda.synchronize()
     assert np.abs(host(Yd) - ref).max() <= tol
+
+
+def test_band_pass_step_and_solve(cs):
+    """Every projector term in the band pass, carried between the filter's applications
+    (the coefficients of each application's output come from the same pass): an FP64 step
+    against the oracle's, bitwise repeatable, and a mixed solve against the oracle."""
+    prob = inputs.small_problem(n=(26, 22, 30), h=(0.3, 0.3, 0.3), bc=(0, 0, 1), fd_order=12, n_atoms=10,
+                                nproj_per_atom=4, seed=31)
+    ns, degree = 20, 9
+    x0 = inputs.initial_block(prob.nd, ns, 5).T
+    lo, cut, hi = oc.spectral_bounds(prob)
+    d_ref, x_ref = oc.chefsi_step(prob, x0, degree, lo, cut, hi)
+    h = cs.Handle(prob, precision=cs.FP64, max_ns=ns)
+    h.chefsi_set_projector_pass(False)
+    ws = cs.workspace(h, ns)
+    outs = []
+    for _ in range(2):
+        Xd = dev(x0)
+        d = h.chefsi_step(Xd, ns, degree, lo, cut, hi, ws)
+        torch.cuda.synchronize()
+        outs.append((d, host(Xd)))
+    assert np.abs(outs[0][0] - d_ref).max() <= 1e-10
+    k = oc.gap_index(d_ref, 16)
+    assert oc.subspace_residual(x_ref, outs[0][1], k) <= 1e-8
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    h.close()
+    # mixed: n_iter - 1 mixed steps + the FP64 refinement, against the oracle's n_iter steps
+    n_iter = 5
+    d_ref, x_ref = oc.chefsi(prob, x0, degree, n_iter, lo, cut, hi)
+    hm = cs.Handle(prob, precision=cs.MIXED, max_ns=ns)
+    hm.chefsi_set_projector_pass(False)
+    wsm = cs.workspace(hm, ns)
+    Xm = dev(x0, "float32")
+    d, _, _ = hm.solve(Xm, ns, degree, n_iter, wsm, bounds=(lo, cut, hi))
+    k = oc.gap_index(d_ref, int(ns / 1.2))
+    assert np.abs(d[:k] - d_ref[:k]).max() <= 1e-5
+    assert oc.subspace_residual(x_ref, host(Xm), k) <= 1e-5
