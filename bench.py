@@ -509,8 +509,12 @@ def main():
     dominant = max(("hx_apply", "gram", "rotate"), key=lambda k: kern[k]["ms_per_step"])
     traffic = None
     if os.path.exists(TRAFFIC_FILE) and precision == "fp64" and cfg.name == "cfg2":
+        # counters of the same kernel source in the same launch configuration only
         t = json.load(open(TRAFFIC_FILE))
-        if t.get("source_sha256_16") == kernel_source_hash("hx_apply.hip"):
+        sc = main_run["stencil_choice"]
+        same = all(t.get("stencil_choice", {}).get(k) == sc[k]
+                   for k in ("rows_per_thread", "row_groups", "projectors_in_stencil"))
+        if t.get("source_sha256_16") == kernel_source_hash("hx_apply.hip") and same:
             traffic = t.get("bytes_per_launch")
     g = main_run["gemm"]
     if dominant in ("gram", "rotate"):
