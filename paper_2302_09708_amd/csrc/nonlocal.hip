@@ -146,9 +146,10 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
 }
 
 // Orbitals per band block: the region's final values of G orbitals sit in LDS
-// (kBandMaxPts * G * sizeof(TC) = 64 KB).
+// (kBandMaxPts * G * sizeof(TC) = 32 KB, plus 16 KB of staged coefficients); measured
+// against 4/8 and 16/32 orbitals per block, this count was the fastest.
 template <typename TC>
-constexpr int band_g() { return sizeof(TC) == 8 ? 4 : 8; }
+constexpr int band_g() { return sizeof(TC) == 8 ? 8 : 16; }
 
 // Blocks are dealt to the 8 XCDs in turn and each XCD takes a contiguous run of logical
 // ids, region-major with the orbital group fastest: the blocks resident on an XCD share one
