@@ -2694,6 +2694,11 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
     check(max_ns >= 1 && (int64_t)max_ns <= nd && max_ns <= 65535, "max_ns must satisfy 1 <= max_ns <= min(Nd, 65535)");
     // the library products (zgemm) take the whole block at once: keep it below 2^31 elements
     check(nd * max_ns < (int64_t)1 << 31, "k-point blocks of 2^31 or more elements (Nd * max_ns) are not supported");
+    {
+      const ZTiling zt = plan_zhx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2);
+      check(grid->n[0] <= kZMaxThreads && zt.kh <= 4 && zt.lds_bytes <= 96 * 1024,
+            "grid too wide in x for the complex stencil tiling (halo values per thread above four)");
+    }
     h->nd = nd;
     h->max_ns = max_ns;
     h->w = fd_weights(grid->fd_order);

@@ -340,6 +340,16 @@ struct ZHxArgs {
   double sa, sc, sb;
 };
 
+// tiling of the complex stencil pass (one row of a tile per thread)
+constexpr int kZMaxThreads = 512;
+struct ZTiling {
+  int ty, nty, zc, nzc, threads, pitch, kh;
+  size_t lds_bytes;
+  int64_t nblocks;
+  int per_xcd;
+};
+ZTiling plan_zhx(int nx, int ny, int nz, int ns, int radius);
+
 struct ZNlArgs {
   const double2* x;
   int64_t nd;

@@ -9,6 +9,8 @@
 // Every sum runs in a fixed order: results are bitwise reproducible.
 #include "common.h"
 
+#include <algorithm>
+
 namespace chefsi {
 
 namespace {
@@ -20,92 +22,210 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// x~(i + p e_d) for one direction: the wrapped neighbour times the cell phase (periodic),
-// or zero outside a Dirichlet boundary.  Periodic directions have n >= r, so i + p wraps
-// at most once.
-__device__ __forceinline__ double2 neighbour(const double2* __restrict__ xv, int64_t i, int c, int p, int n,
-                                             int64_t stride, int periodic, double2 ph) {
-  int j = c + p;
-  if (j >= n) {
-    if (!periodic) return make_double2(0.0, 0.0);
-    return cmul(xv[i + (int64_t)(j - n - c) * stride], ph);
-  }
-  if (j < 0) {
-    if (!periodic) return make_double2(0.0, 0.0);
-    return cmul(xv[i + (int64_t)(j + n - c) * stride], make_double2(ph.x, -ph.y));
-  }
-  return xv[i + (int64_t)p * stride];
+// ---------------------------------------------------------------------------
+// zhx: the Bloch-phased stencil pass, laid out like the real one.  One block = one orbital
+// x a tile of whole x rows (ty rows, one row per thread) x a chunk of z planes; the block
+// marches through z with the 2r+1 z neighbours of its column in registers, and stages each
+// plane of the tile plus r halo rows (and r periodic copies on each side of every row) in
+// double-buffered LDS.  Every value that crosses a periodic face carries the cell phase
+// exp(+-i k_d L_d) of that face: the staged slots keep their phase (a constant per slot),
+// the z queue multiplies the plane's phase into its loads, and rows past ny of the last
+// tile (periodic y) carry exp(i k_y L_y).  Zero ghosts of Dirichlet faces are buffer loads
+// past the end of the resource (no branch).
+// ---------------------------------------------------------------------------
+constexpr unsigned kZOOB = 0x80000000u;
+constexpr int kZDummy = 64;  // per-lane dummy LDS slots after each buffer
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t zrsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-
-constexpr int kZTx = 32, kZTy = 16;  // plane tile of one block (512 threads)
-constexpr int kZLx = kZTx + 2 * kMaxRadius, kZLy = kZTy + 2 * kMaxRadius;
-
-// x~ at (gx, gy) of plane z for any gx, gy within r of the grid: wrapped with the cell
-// phases in periodic directions, zero outside a Dirichlet boundary.
-__device__ __forceinline__ double2 plane_value(const double2* __restrict__ xv, int gx, int gy, int64_t zoff,
-                                               const ZHxArgs& a) {
+__device__ __forceinline__ double2 zload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+  return make_double2(__builtin_bit_cast(double, (unsigned long long)v0 | ((unsigned long long)v1 << 32)),
+                      __builtin_bit_cast(double, (unsigned long long)v2 | ((unsigned long long)v3 << 32)));
+}
+__device__ __forceinline__ void zstore(__amdgpu_buffer_rsrc_t r, double2 v, unsigned voff, unsigned soff) {
+  typedef unsigned u32x4z __attribute__((__vector_size__(16)));
+  const unsigned long long a = __builtin_bit_cast(unsigned long long, v.x);
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v.y);
+  u32x4z w = {(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, voff, soff, 0);
+}
+__device__ __forceinline__ unsigned zoff(int e) { return e < 0 ? kZOOB : (unsigned)e * 16u; }
+__device__ __forceinline__ double2 zpow(double2 ph, int k) {  // ph^k, k of either sign
   double2 f = make_double2(1.0, 0.0);
-  const int g[2] = {gx, gy};
-  int w[2];
-  for (int d = 0; d < 2; ++d) {
-    const int n = a.n[d];
-    int c = g[d], k = 0;
-    while (c >= n) { c -= n; ++k; }
-    while (c < 0) { c += n; --k; }
-    if (k != 0) {
-      if (!a.per[d]) return make_double2(0.0, 0.0);
-      const double2 ph = k > 0 ? a.ph[d] : make_double2(a.ph[d].x, -a.ph[d].y);
-      for (int t = 0; t < (k > 0 ? k : -k); ++t) f = cmul(f, ph);
-    }
-    w[d] = c;
-  }
-  return cmul(xv[zoff + w[0] + (int64_t)a.n[0] * w[1]], f);
+  const double2 b = k >= 0 ? ph : make_double2(ph.x, -ph.y);
+  for (int t = 0; t < (k >= 0 ? k : -k); ++t) f = cmul(f, b);
+  return f;
+}
+// wrap c into [0, n): the wrapped index and the number of cells crossed (k)
+__device__ __forceinline__ int zwrap(int c, int n, int& k) {
+  k = 0;
+  while (c >= n) { c -= n; ++k; }
+  while (c < 0) { c += n; --k; }
+  return c;
 }
 
-// One block per (32 x 16 tile of a plane, plane z, orbital): the tile and its r-wide x and y
-// halos are staged once in LDS (Bloch phases and Dirichlet zeros applied while staging),
-// the x and y neighbours come from LDS, the 2r z neighbours of every point from global
-// memory (through the caches).
-__global__ __launch_bounds__(kZTx * kZTy) void zhx_kernel(ZHxArgs a) {
-  __shared__ double2 tile[kZLy][kZLx];
+template <int R, int KH>
+__global__ __launch_bounds__(kZMaxThreads) void zhx_kernel(ZHxArgs a, ZTiling t) {
+  extern __shared__ __align__(16) unsigned char zlds[];
+  constexpr int Q = 2 * R + 1;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const int tiles_x = (nx + kZTx - 1) / kZTx;
-  const int x0 = (blockIdx.x % tiles_x) * kZTx, y0 = (blockIdx.x / tiles_x) * kZTy;
-  const int z = blockIdx.y;
-  const int64_t v = blockIdx.z;
-  const int R = a.r;
-  const int64_t pstride = (int64_t)nx * ny;
-  const double2* __restrict__ xv = a.x + v * a.nd;
-  const int tid = threadIdx.x;
-  const int lw = kZTx + 2 * R, lh = kZTy + 2 * R;
-  for (int e = tid; e < lw * lh; e += kZTx * kZTy) {
-    const int ly = e / lw, lx = e % lw;
-    tile[ly][lx] = plane_value(xv, x0 + lx - R, y0 + ly - R, pstride * z, a);
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * t.per_xcd + blockIdx.x / 8;
+  if (logical >= t.nblocks) return;
+  const int per_vec = t.nty * t.nzc;
+  const int64_t vec = logical / per_vec;
+  const int rem = (int)(logical % per_vec);
+  const int y0 = (rem % t.nty) * t.ty, z0 = (rem / t.nty) * t.zc;
+  const int z1 = min(z0 + t.zc, nz);
+  const int nzl = z1 - z0;
+  const int pitch = t.pitch;
+  const int tile_elems = (t.ty + 2 * R) * pitch, tile_buf = tile_elems + kZDummy;
+  double2* lt = reinterpret_cast<double2*>(zlds);
+
+  const int nplane = nx * ny;
+  const int xbytes = (int)(a.nd * 16);
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(a.x + vec * a.nd, xbytes);
+  const __amdgpu_buffer_rsrc_t rzero = zrsrc(a.x, 0);
+  const __amdgpu_buffer_rsrc_t rv = zrsrc(a.veff, a.nd * 8);
+  const bool has_prev = a.prev != nullptr;
+  const __amdgpu_buffer_rsrc_t rp = zrsrc(has_prev ? (const void*)(a.prev + vec * a.nd) : (const void*)a.out,
+                                          has_prev ? xbytes : 0);
+  const __amdgpu_buffer_rsrc_t ro = zrsrc(a.out + vec * a.nd, xbytes);
+
+  // the thread's row: offset in a plane (kZOOB for a Dirichlet zero row), the phase of a
+  // wrapped row, whether its output is stored, and its LDS slot (a dummy for idle lanes)
+  const bool active = tid < nx * t.ty;
+  const int x = active ? tid % nx : 0, ly = active ? tid / nx : 0;
+  const int gy = y0 + ly;
+  int ky;
+  const int wy = zwrap(gy, ny, ky);
+  const bool rowzero = !active || (ky != 0 && !a.per[1]);
+  const unsigned vq = rowzero ? kZOOB : (unsigned)(x + nx * wy) * 16u;
+  const double2 rowph = zpow(a.ph[1], ky);
+  const bool valid = active && gy < ny;
+  const unsigned vo = valid ? (unsigned)(x + nx * gy) * 16u : kZOOB;
+  const unsigned vv = valid ? (unsigned)(x + nx * gy) * 8u : kZOOB;
+  const int sown = active ? (R + ly) * pitch + R + x : tile_elems + lane;
+
+  // staged slots: halo rows (and, with a periodic x, the r copies on each side of every row)
+  int sdst[KH];
+  unsigned vh[KH];
+  double2 sph[KH];
+  {
+    const int w = a.per[0] ? nx + 2 * R : nx;
+    const int nslots = 2 * R * w + (a.per[0] ? t.ty * 2 * R : 0);
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int e = tid + k * nthr;
+      sdst[k] = tile_elems + lane;
+      vh[k] = kZOOB;
+      sph[k] = make_double2(1.0, 0.0);
+      if (e < nslots) {
+        int yy, c;
+        if (e < 2 * R * w) {
+          const int hr = e / w;
+          c = e % w + (a.per[0] ? 0 : R);
+          yy = hr < R ? hr : hr + t.ty;
+        } else {
+          const int f = e - 2 * R * w;
+          const int cc = f % (2 * R);
+          c = cc < R ? cc : nx + cc;
+          yy = R + f / (2 * R);
+        }
+        int kx, kyy;
+        const int sx = zwrap(c - R, nx, kx);
+        const int sy = zwrap(y0 - R + yy, ny, kyy);
+        sdst[k] = yy * pitch + c;
+        const bool zero = (kx != 0 && !a.per[0]) || (kyy != 0 && !a.per[1]);
+        vh[k] = zero ? kZOOB : (unsigned)(sx + nx * sy) * 16u;
+        sph[k] = cmul(zpow(a.ph[0], kx), zpow(a.ph[1], kyy));
+      }
+    }
   }
-  __syncthreads();
-  const int tx = tid % kZTx, ty = tid / kZTx;
-  const int x = x0 + tx, y = y0 + ty;
-  if (x >= nx || y >= ny) return;
-  const int64_t i = x + (int64_t)nx * y + pstride * z;
-  const double2 xi = tile[ty + R][tx + R];
-  const double diag = a.c0 + a.veff[i] - a.sc;
-  double re = diag * xi.x, im = diag * xi.y;
-  const double2* col = xv + x + (int64_t)nx * y;
-  for (int p = 1; p <= R; ++p) {
-    const double2 xu = tile[ty + R][tx + R + p], xd = tile[ty + R][tx + R - p];
-    const double2 yu = tile[ty + R + p][tx + R], yd = tile[ty + R - p][tx + R];
-    const double2 zu = neighbour(col, pstride * z, z, p, nz, pstride, a.per[2], a.ph[2]);
-    const double2 zd = neighbour(col, pstride * z, z, -p, nz, pstride, a.per[2], a.ph[2]);
-    re += a.cw[0][p] * (xu.x + xd.x) + a.cw[1][p] * (yu.x + yd.x) + a.cw[2][p] * (zu.x + zd.x);
-    im += a.cw[0][p] * (xu.y + xd.y) + a.cw[1][p] * (yu.y + yd.y) + a.cw[2][p] * (zu.y + zd.y);
+
+  // plane p of the z queue: the wrapped plane's byte offset and resource, and its phase
+  auto qplane = [&](int p, __amdgpu_buffer_rsrc_t& r, unsigned& so, double2& ph) {
+    int kz;
+    const int wz = zwrap(p, nz, kz);
+    const bool zero = kz != 0 && !a.per[2];
+    r = zero ? rzero : rx;
+    so = zero ? 0u : (unsigned)wz * (unsigned)nplane * 16u;
+    ph = cmul(zpow(a.ph[2], kz), rowph);
+  };
+
+  double2 q[Q], pf, hp[KH];
+  q[0] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int s = 1; s < Q; ++s) {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned so;
+    double2 ph;
+    qplane(z0 - R - 1 + s, r, so, ph);
+    q[s] = cmul(zload(r, vq, so), ph);
   }
-  double2 o = make_double2(a.sa * re, a.sa * im);
-  if (a.prev != nullptr) {
-    const double2 pv = a.prev[v * a.nd + i];
-    o.x += a.sb * pv.x;
-    o.y += a.sb * pv.y;
+  __amdgpu_buffer_rsrc_t rpf;
+  unsigned spf;
+  double2 phf;
+  qplane(z0 + R, rpf, spf, phf);
+  pf = zload(rpf, vq, spf);
+#pragma unroll
+  for (int k = 0; k < KH; ++k) hp[k] = zload(rx, vh[k], (unsigned)z0 * (unsigned)nplane * 16u);
+
+  if (!a.per[0]) {  // Dirichlet x: the halo columns of both buffers hold zeros
+    const int rows = 2 * (t.ty + 2 * R);
+    for (int i = tid; i < rows * 2 * R; i += nthr) {
+      const int row = i / (2 * R), c = i % (2 * R);
+      const int buf = row / (t.ty + 2 * R), rr = row % (t.ty + 2 * R);
+      lt[buf * tile_buf + rr * pitch + (c < R ? c : nx + c)] = make_double2(0.0, 0.0);
+    }
   }
-  a.out[v * a.nd + i] = o;
+
+  for (int zl = 0; zl < nzl; ++zl) {
+    const int z = z0 + zl;
+    double2* tl = lt + (zl & 1) * tile_buf;
+    const bool more = zl + 1 < nzl;
+    const unsigned zo = (unsigned)z * (unsigned)nplane;
+    const double vz = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, vv, zo * 8u, 0));
+    const double2 cp = zload(rp, vo, zo * 16u);
+    // advance the queue (the fetched plane's phase applied now); fetch plane z + R + 1
+#pragma unroll
+    for (int s = 0; s < Q - 1; ++s) q[s] = q[s + 1];
+    q[Q - 1] = cmul(pf, phf);
+    if (more) qplane(z + R + 1, rpf, spf, phf);
+    else {
+      rpf = rzero;
+      spf = 0u;
+    }
+    pf = zload(rpf, vq, spf);
+    // stage plane z; fetch the staged values of plane z + 1
+    tl[sown] = q[R];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) tl[sdst[k]] = cmul(hp[k], sph[k]);
+    {
+      const __amdgpu_buffer_rsrc_t r = more ? rx : rzero;
+      const unsigned so = more ? (unsigned)(z + 1) * (unsigned)nplane * 16u : 0u;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hp[k] = zload(r, vh[k], so);
+    }
+    __syncthreads();
+
+    const double2 xc = q[R];
+    const double dg = a.c0 + vz - a.sc;
+    double re = dg * xc.x, im = dg * xc.y;
+    const double2* row = tl + (R + ly) * pitch + R + x;
+#pragma unroll
+    for (int p = 1; p <= R; ++p) {
+      const double2 xu = row[p], xd = row[-p];
+      const double2 yu = row[p * pitch], yd = row[-p * pitch];
+      const double2 zu = q[R + p], zd = q[R - p];
+      re += a.cw[0][p] * (xu.x + xd.x) + a.cw[1][p] * (yu.x + yd.x) + a.cw[2][p] * (zu.x + zd.x);
+      im += a.cw[0][p] * (xu.y + xd.y) + a.cw[1][p] * (yu.y + yd.y) + a.cw[2][p] * (zu.y + zd.y);
+    }
+    zstore(ro, make_double2(a.sa * re + a.sb * cp.x, a.sa * im + a.sb * cp.y), vo, zo * 16u);
+  }
 }
 
 constexpr int kZThreads = 256;
@@ -228,13 +348,54 @@ hipError_t launch_zsum_partials(const double2* P, int nparts, int ns, double2* C
   return hipGetLastError();
 }
 
+ZTiling plan_zhx(int nx, int ny, int nz, int ns, int radius) {
+  ZTiling t{};
+  // rows per tile: whole x rows, one per thread, at most kZMaxThreads threads; at least
+  // r + 1 rows when they fit (thinner tiles read the halo more than twice per row)
+  t.ty = std::max(1, std::min(ny, kZMaxThreads / std::max(1, nx)));
+  t.nty = (ny + t.ty - 1) / t.ty;
+  t.threads = ((nx * t.ty + 63) / 64) * 64;
+  t.pitch = nx + std::max(16, ((2 * radius + 15) / 16) * 16);  // row gap of 256 bytes: distinct banks
+  const int w = nx + 2 * radius;
+  const int nslots = 2 * radius * w + t.ty * 2 * radius;
+  t.kh = std::max(2, (nslots + t.threads - 1) / t.threads);
+  const int64_t xy = (int64_t)t.nty * ns;
+  int nzc = (int)std::max<int64_t>(1, (2048 + xy - 1) / xy);
+  nzc = std::min(nzc, std::max(1, nz / std::max(1, 2 * radius)));
+  t.zc = (nz + nzc - 1) / nzc;
+  t.nzc = (nz + t.zc - 1) / t.zc;
+  t.lds_bytes = 2 * ((size_t)(t.ty + 2 * radius) * t.pitch + kZDummy) * 16;
+  return t;
+}
+
+template <int R>
+static hipError_t launch_zhx_r(const ZHxArgs& a, ZTiling t, int ns, hipStream_t s) {
+  t.nblocks = (int64_t)t.nty * t.nzc * ns;
+  t.per_xcd = (int)((t.nblocks + 7) / 8);
+  const dim3 grid((unsigned)(t.per_xcd * 8));
+  switch (t.kh) {
+    case 2: hipLaunchKernelGGL((zhx_kernel<R, 2>), grid, dim3(t.threads), t.lds_bytes, s, a, t); break;
+    case 3: hipLaunchKernelGGL((zhx_kernel<R, 3>), grid, dim3(t.threads), t.lds_bytes, s, a, t); break;
+    case 4: hipLaunchKernelGGL((zhx_kernel<R, 4>), grid, dim3(t.threads), t.lds_bytes, s, a, t); break;
+    default: return hipErrorInvalidConfiguration;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s) {
   if (a.nd <= 0 || ns <= 0) return hipSuccess;
-  if (a.r < 1 || a.r > kMaxRadius || a.n[2] > 65535) return hipErrorInvalidValue;
-  const int tiles = ((a.n[0] + kZTx - 1) / kZTx) * ((a.n[1] + kZTy - 1) / kZTy);
-  dim3 grid((unsigned)tiles, (unsigned)a.n[2], (unsigned)ns);
-  hipLaunchKernelGGL(zhx_kernel, grid, dim3(kZTx * kZTy), 0, s, a);
-  return hipGetLastError();
+  if (a.r < 1 || a.r > kMaxRadius || a.n[0] > kZMaxThreads) return hipErrorInvalidValue;
+  const ZTiling t = plan_zhx(a.n[0], a.n[1], a.n[2], ns, a.r);
+  if (t.kh > 4 || t.lds_bytes > 96 * 1024) return hipErrorInvalidConfiguration;
+  switch (a.r) {
+    case 1: return launch_zhx_r<1>(a, t, ns, s);
+    case 2: return launch_zhx_r<2>(a, t, ns, s);
+    case 3: return launch_zhx_r<3>(a, t, ns, s);
+    case 4: return launch_zhx_r<4>(a, t, ns, s);
+    case 5: return launch_zhx_r<5>(a, t, ns, s);
+    case 6: return launch_zhx_r<6>(a, t, ns, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s) {

@@ -31,6 +31,12 @@ CASES = [
      (-0.9, 0.35, 0.6)),
     ("order4_ragged", dict(n=(17, 11, 13), h=(0.3, 0.35, 0.33), bc=(0, 1, 0), fd_order=4, n_atoms=3,
                            nproj_per_atom=1, seed=23), (1.3, 0.0, -0.45)),
+    # 40 wide: tiles of 12 rows, so 29 rows are three tiles with a ragged last one (rows past
+    # ny carry the y phase, or are zeros with a Dirichlet y), and the z march runs in chunks
+    ("tiles_periodic", dict(n=(40, 29, 18), h=(0.3, 0.31, 0.29), bc=(0, 0, 0), n_atoms=5, nproj_per_atom=4,
+                            seed=24), (0.55, -1.1, 0.8)),
+    ("tiles_dirichlet_xy", dict(n=(40, 29, 18), h=(0.3, 0.31, 0.29), bc=(1, 1, 0), n_atoms=5, nproj_per_atom=4,
+                                seed=25), (0.0, 0.0, -0.6)),
 ]
 
 
