@@ -380,8 +380,9 @@ int chefsi_version(void);
  * (ns, Nd).  A step is Alg. 1 with conjugate transposes: Hs = X~^H H X~,
  * Ms = X~^H X~, Hs Z = Ms Z D (Hermitian definite, ascending D), X = X~ Z.
  * The handle holds its own copies of all host inputs (freed by
- * chefsi_kpoint_destroy); calls are ordered on their stream; max_ns <= 65535 and
- * Nd * max_ns < 2^31 (CHEFSI_ERR_INVALID_ARG otherwise).
+ * chefsi_kpoint_destroy); calls are ordered on their stream; Nd < 2^31 and
+ * max_ns <= min(Nd, 65535) (CHEFSI_ERR_INVALID_ARG otherwise); a block may hold
+ * 2^31 elements or more (the rotation runs in row panels below that size).
  * Errors as for the real handle (INVALID_ARG, WORKSPACE, NOT_POSDEF, EIG,
  * NONFINITE, SOLVER, HIP, OOM); after an error the handle stays usable and X
  * is unspecified. */

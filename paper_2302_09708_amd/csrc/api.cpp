@@ -2510,9 +2510,10 @@ size_t zsolver_workspace(chefsi_kpoint* h, int ns) {
     rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one, nullptr,
                   ld, nullptr, ld, &one, nullptr, ns);
   });
+  const rocblas_int prow = (rocblas_int)std::max<int64_t>(1, std::min<int64_t>(h->nd, (((int64_t)1 << 31) - 1) / ns));
   query([&] {
-    rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, ld, ns, ns, &one, nullptr, ld, nullptr, ns,
-                  &one, nullptr, ld);
+    rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, prow, ns, ns, &one, nullptr, ld, nullptr,
+                  ns, &one, nullptr, ld);
   });
   h->solver_ws_cache[ns] = best;
   return best;
@@ -2692,8 +2693,6 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
     }
     check(nd < (int64_t)1 << 31, "Nd must be below 2^31");
     check(max_ns >= 1 && (int64_t)max_ns <= nd && max_ns <= 65535, "max_ns must satisfy 1 <= max_ns <= min(Nd, 65535)");
-    // the library products (zgemm) take the whole block at once: keep it below 2^31 elements
-    check(nd * max_ns < (int64_t)1 << 31, "k-point blocks of 2^31 or more elements (Nd * max_ns) are not supported");
     {
       const ZTiling zt = plan_zhx(grid->n[0], grid->n[1], grid->n[2], 1, grid->fd_order / 2);
       check(grid->n[0] <= kZMaxThreads && zt.kh <= 4 && zt.lds_bytes <= 96 * 1024,
@@ -2923,9 +2922,14 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
                               zat<double>(ws, L.e), info + 1));
     BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                            rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
-    // rotation (Alg. 1, Rotation): X = X~ Z into the buffer Y~ held
-    BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, ld, ns, ns, &one, zc(Xf), ld,
-                           zc(Hs), ns, &zero, zm(Yf), ld));
+    // rotation (Alg. 1, Rotation): X = X~ Z into the buffer Y~ held, in row panels of fewer
+    // than 2^31 output elements each (blocks of any size)
+    const int64_t prow = std::max<int64_t>(1, std::min<int64_t>(h->nd, (((int64_t)1 << 31) - 1) / ns));
+    for (int64_t r0 = 0; r0 < h->nd; r0 += prow) {
+      const rocblas_int m = (rocblas_int)std::min<int64_t>(prow, h->nd - r0);
+      BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, m, ns, ns, &one, zc(Xf + r0),
+                             ld, zc(Hs), ns, &zero, zm(Yf + r0), ld));
+    }
     if (Yf != A) HIP_TRY(hipMemcpyAsync(A, Yf, (size_t)h->nd * ns * 16, hipMemcpyDeviceToDevice, s));
     double* d = h->pinned;
     rocblas_int* inf = reinterpret_cast<rocblas_int*>(h->pinned + h->max_ns);

@@ -184,3 +184,52 @@ def test_apply_h_full_size_sampled(cs):
         print(f"  column {j}: max rel err {err:.2e}", flush=True)
         assert err < 1e-12
     h.close()
+
+
+def test_block_above_2_31_elements(cs):
+    """A block of 2^31 complex elements or more (120^3 grid with 1000 atoms x 4 projectors,
+    Ns = 1300: 2.25e9 elements, 36 GB): sampled columns of H_k X on both sides of element
+    2^31 against the oracle, then one step checked by what holds at any size: X^H X = I and
+    X^H H_k X = diag(D), over both row panels of the rotation."""
+    prob = inputs.make_problem(inputs.CONFIGS["cfg4"])
+    img = inputs.support_images(prob)
+    k = tuple(np.pi / (2.0 * prob.n[d] * prob.h[d]) for d in range(3))
+    ns = 1300
+    assert prob.nd * ns >= 1 << 31
+    hr = cs.Handle(prob, precision=cs.FP64, max_ns=1)
+    lo, cut, hi = hr.chefsi_spectral_bounds()
+    hr.close()
+    h = cs.KPoint(prob, k, img, max_ns=ns)
+    ws = h.workspace(ns)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(78)
+    X = torch.randn((ns, prob.nd), generator=g, device="cuda", dtype=torch.complex128)
+    Y = torch.empty_like(X)
+    print(f"apply_h above 2^31 n={prob.n} ns={ns}", flush=True)
+    h.apply_h(X, Y, ns, ws)
+    torch.cuda.synchronize()
+    first_high = (1 << 31) // prob.nd  # first column holding element 2^31
+    for j in (0, first_high, ns - 1):
+        ref = ok.apply_h_k(prob, img, k, X[j].cpu().numpy()[:, None])[:, 0]
+        err = np.abs(Y[j].cpu().numpy() - ref).max() / np.abs(ref).max()
+        print(f"  column {j}: max rel err {err:.2e}", flush=True)
+        assert err < 1e-12
+    print(f"step above 2^31 degree 4 bounds ({lo:.3f}, {cut:.3f}, {hi:.3f})", flush=True)
+    d = h.step(X, ns, 4, lo, cut, hi, ws)
+    h.apply_h(X, Y, ns, ws)
+    G = torch.zeros((ns, ns), dtype=torch.complex128, device="cuda")
+    R = torch.zeros_like(G)
+    step = 1 << 17
+    for r0 in range(0, prob.nd, step):
+        xc = X[:, r0:r0 + step]
+        G += xc.conj() @ xc.T.contiguous()
+        R += xc.conj() @ Y[:, r0:r0 + step].T.contiguous()
+    torch.cuda.synchronize()
+    eye = torch.eye(ns, dtype=torch.complex128, device="cuda")
+    orth = (G - eye).abs().max().item()
+    dd = torch.from_numpy(d).to(device="cuda", dtype=torch.complex128)
+    ritz = (R - torch.diag(dd)).abs().max().item() / np.abs(d).max()
+    print(f"  |X^H X - I| {orth:.2e}, |X^H H X - D| / |D| {ritz:.2e}", flush=True)
+    assert orth < 1e-10
+    assert ritz < 1e-10
+    h.close()
