@@ -1153,82 +1153,69 @@ void free_band_tables(chefsi_handle* h) {
   h->nb_reg = h->nb_pts = h->nb_slots = 0;
 }
 
-// Band-pass tables from the point-major projector table: regions of one z plane x a band of
-// rows, the band height the largest with at most kBandMaxPts touched points per region;
-// each region lists its touched points (index order) with their entries, and its projector
-// slots (projector order) with their entries (point order); each projector lists its slots
-// (region order) for the reduction.
+// Band-pass tables from the point-major projector table: regions of consecutive touched
+// points (grid index order), each closed before it would exceed kBandMaxPts points,
+// kBandMaxSlots projectors or kBandMaxEnt entries; each region lists its points with their
+// entries, and its projector slots (projector order) with their entries (point order);
+// each projector lists its slots (region order) for the reduction.
 void build_band_tables(chefsi_handle* h) {
   free_band_tables(h);
-  const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
   const std::vector<int>& cnt = h->pt_cnt;
-  std::vector<int> row_pts((size_t)ny * nz, 0);
-  for (int64_t i = 0; i < h->nd; ++i)
-    if (cnt[i + 1] > cnt[i]) row_pts[i / nx] += 1;
-  // projectors touching each row (for the slot bound)
-  std::vector<std::vector<int>> row_q((size_t)ny * nz);
-  for (int64_t i = 0; i < h->nd; ++i)
-    for (int e = cnt[i]; e < cnt[i + 1]; ++e) row_q[i / nx].push_back(h->pt_col[e]);
-  for (auto& v : row_q) {
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-  }
-  auto fits = [&](int hb) {
-    for (int z = 0; z < nz; ++z)
-      for (int y0 = 0; y0 < ny; y0 += hb) {
-        int c = 0;
-        std::vector<int> qs;
-        for (int y = y0; y < std::min(ny, y0 + hb); ++y) {
-          c += row_pts[(size_t)z * ny + y];
-          qs.insert(qs.end(), row_q[(size_t)z * ny + y].begin(), row_q[(size_t)z * ny + y].end());
-        }
-        std::sort(qs.begin(), qs.end());
-        qs.erase(std::unique(qs.begin(), qs.end()), qs.end());
-        if (c > kBandMaxPts || (int)qs.size() > kBandMaxSlots) return false;
-      }
-    return true;
-  };
-  check(fits(1), "a grid row holds too many touched points or projectors for the band pass");
-  int hb = 1;
-  while (hb < ny && fits(hb + 1)) ++hb;
-  const int nbands = (ny + hb - 1) / hb;
   std::vector<int> reg_pt(1, 0), pt_idx, pt_ent(1, 0), ent_q, ent_ls, reg_slot(1, 0), slot_ent(1, 0), gent_loc,
       slot_q;
   std::vector<double> ent_chi, gent_chi;
   std::vector<std::vector<int>> q_slots(h->np_tot);
-  for (int z = 0; z < nz; ++z)
-    for (int b = 0; b < nbands; ++b) {
-      const int first = (int)pt_idx.size();
-      std::map<int, std::vector<std::pair<int, double>>> slots;  // projector -> (local point, chi)
-      for (int y = b * hb; y < std::min(ny, (b + 1) * hb); ++y)
-        for (int x = 0; x < nx; ++x) {
-          const int64_t i = x + (int64_t)nx * (y + (int64_t)ny * z);
-          if (cnt[i + 1] == cnt[i]) continue;
-          const int loc = (int)pt_idx.size() - first;
-          pt_idx.push_back((int)i);
-          for (int e = cnt[i]; e < cnt[i + 1]; ++e) {
-            ent_q.push_back(h->pt_col[e]);
-            ent_chi.push_back(h->pt_val[e]);
-            slots[h->pt_col[e]].emplace_back(loc, h->pt_val[e]);
-          }
-          pt_ent.push_back((int)ent_q.size());
-        }
-      reg_pt.push_back((int)pt_idx.size());
-      // region slot of every entry of the region's points (slots in projector order)
-      std::map<int, int> local;
-      for (auto& kv : slots) local.emplace(kv.first, (int)local.size());
-      for (size_t e = ent_ls.size(); e < ent_q.size(); ++e) ent_ls.push_back(local.at(ent_q[e]));
-      for (auto& kv : slots) {
-        q_slots[kv.first].push_back((int)slot_q.size());
-        slot_q.push_back(kv.first);
-        for (auto& pe : kv.second) {
-          gent_loc.push_back(pe.first);
-          gent_chi.push_back(pe.second);
-        }
-        slot_ent.push_back((int)gent_loc.size());
+  std::vector<int64_t> open;           // points of the open region
+  std::vector<int> stamp(h->np_tot, -1);  // region that last counted each projector
+  int nreg = 0, open_ent = 0, open_q = 0;
+  auto close_region = [&]() {
+    const int first = (int)pt_idx.size();
+    std::map<int, std::vector<std::pair<int, double>>> slots;  // projector -> (local point, chi)
+    for (int64_t i : open) {
+      const int loc = (int)pt_idx.size() - first;
+      pt_idx.push_back((int)i);
+      for (int e = cnt[i]; e < cnt[i + 1]; ++e) {
+        ent_q.push_back(h->pt_col[e]);
+        ent_chi.push_back(h->pt_val[e]);
+        slots[h->pt_col[e]].emplace_back(loc, h->pt_val[e]);
       }
-      reg_slot.push_back((int)slot_q.size());
+      pt_ent.push_back((int)ent_q.size());
     }
+    reg_pt.push_back((int)pt_idx.size());
+    std::map<int, int> local;  // region slot of every entry (slots in projector order)
+    for (auto& kv : slots) local.emplace(kv.first, (int)local.size());
+    for (size_t e = ent_ls.size(); e < ent_q.size(); ++e) ent_ls.push_back(local.at(ent_q[e]));
+    for (auto& kv : slots) {
+      q_slots[kv.first].push_back((int)slot_q.size());
+      slot_q.push_back(kv.first);
+      for (auto& pe : kv.second) {
+        gent_loc.push_back(pe.first);
+        gent_chi.push_back(pe.second);
+      }
+      slot_ent.push_back((int)gent_loc.size());
+    }
+    reg_slot.push_back((int)slot_q.size());
+    open.clear();
+    open_ent = open_q = 0;
+    ++nreg;
+  };
+  for (int64_t i = 0; i < h->nd; ++i) {
+    const int n = cnt[i + 1] - cnt[i];
+    if (n == 0) continue;
+    check(n <= kBandMaxSlots, "a grid point lies in too many projector supports for the band pass");
+    int fresh = 0;
+    for (int e = cnt[i]; e < cnt[i + 1]; ++e) fresh += stamp[h->pt_col[e]] != nreg;
+    if (!open.empty() && ((int)open.size() + 1 > kBandMaxPts || open_ent + n > kBandMaxEnt ||
+                          open_q + fresh > kBandMaxSlots)) {
+      close_region();
+      fresh = n;  // every projector of the point is new to the next region
+    }
+    for (int e = cnt[i]; e < cnt[i + 1]; ++e) stamp[h->pt_col[e]] = nreg;
+    open.push_back(i);
+    open_ent += n;
+    open_q += fresh;
+  }
+  if (!open.empty()) close_region();
   std::vector<int> q_slot_ptr(1, 0), q_slot;
   for (int q = 0; q < h->np_tot; ++q) {
     for (int sl : q_slots[q]) q_slot.push_back(sl);

@@ -145,8 +145,10 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // nl_band: the whole projector term of H y in one pass over the touched points, region by
-// region (a region = one z plane x a band of rows; its touched points in index order).
-// A block owns one region and G orbitals:
+// region (a region = a run of consecutive touched points in grid index order, packed up to
+// kBandMaxPts points, kBandMaxSlots projectors and kBandMaxEnt projector entries).
+// A block owns one region and a run of orbital groups of G orbitals; it stages the
+// region's entry tables in LDS once and, group by group:
 //   scatter (optional): y[v][i] += sa * sum_{e in entries(i)} chi_e * alpha[q_e][v], written
 //   in place (alpha projector-major: alpha[q * ns + v]);
 //   gather: for every projector q touching the region (a slot), partial[slot][v] =
@@ -154,8 +156,10 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s);
 // and nl_band_reduce forms alpha[q][v] = gdv[q] * sum of q's slots in region order.  Every
 // sum has a fixed order: the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
+constexpr int kBandThreads = 512;   // one thread per point of the region
 constexpr int kBandMaxPts = 512;    // touched points of one region (LDS: kBandMaxPts * G values)
-constexpr int kBandMaxSlots = 256;  // projectors touching one region (their coefficients staged in LDS)
+constexpr int kBandMaxSlots = 128;  // projectors touching one region (their coefficients staged in LDS)
+constexpr int kBandMaxEnt = 1920;   // projector entries of one region (scatter and gather tables in LDS)
 
 template <typename TY, typename TC>
 struct NbArgs {
@@ -177,6 +181,8 @@ struct NbArgs {
   TC sa;
   TC* partial;          // nslots x ns, projector slot major
   int ngroups;          // orbital groups (set by the launcher)
+  int gpc;              // orbital groups per block (set by the launcher)
+  int nchunks;          // blocks per region (set by the launcher)
   int per_xcd;          // blocks per XCD (set by the launcher)
 };
 

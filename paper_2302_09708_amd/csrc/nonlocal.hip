@@ -145,85 +145,142 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Orbitals per band block: the region's final values of G orbitals sit in LDS
-// (kBandMaxPts * G * sizeof(TC) = 32 KB, plus 16 KB of staged coefficients); measured
-// against 4/8 and 16/32 orbitals per block, this count was the fastest.
+// Orbitals per group: a group's final values of the region's points sit in LDS
+// (kBandMaxPts * G * sizeof(TC) = 32 KB) beside the staged coefficients and the entry
+// tables, 80 KB in all, so two blocks share a CU.
 template <typename TC>
 constexpr int band_g() { return sizeof(TC) == 8 ? 8 : 16; }
 
-// Blocks are dealt to the 8 XCDs in turn and each XCD takes a contiguous run of logical
-// ids, region-major with the orbital group fastest: the blocks resident on an XCD share one
-// region's tables (point entries, slot entries) through its L2 while they sweep orbitals.
+// One block per (region, run of orbital groups), one thread per point.  The region's
+// entry tables go to LDS once; then, group by group, the point values and the staged
+// coefficients of the next group are fetched into registers while the current group is
+// scattered and gathered, so the block streams its orbitals with one barrier pair per
+// group.  Blocks are dealt to the 8 XCDs in turn, each XCD taking a contiguous run of
+// logical ids (region-major, run of groups fastest).
 template <typename TY, typename TC, bool SCATTER>
-__global__ __launch_bounds__(256) void nl_band_kernel(NbArgs<TY, TC> a, int gather) {
+__global__ __launch_bounds__(kBandThreads) void nl_band_kernel(NbArgs<TY, TC> a, int gather) {
   constexpr int G = band_g<TC>();
+  constexpr int AJ = (kBandMaxSlots * G + kBandThreads - 1) / kBandThreads;  // staged coefficients per thread
   __shared__ TC ys[kBandMaxPts * G];
   __shared__ TC as[kBandMaxSlots * G];
-  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
-  if (logical >= (int64_t)a.nreg * a.ngroups) return;
-  const int reg = (int)(logical / a.ngroups);
-  const int v0 = (int)(logical % a.ngroups) * G;
-  const int nv = min(G, a.ns - v0);
+  __shared__ TC echi[kBandMaxEnt];
+  __shared__ TC gchi[kBandMaxEnt];
+  __shared__ unsigned short els[kBandMaxEnt];
+  __shared__ unsigned short gloc[kBandMaxEnt];
+  __shared__ int sent[kBandMaxSlots + 1];
+  __shared__ int sq[kBandMaxSlots];
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + (a.per_xcd - 1 - blockIdx.x / 8);
+  if (logical >= (int64_t)a.nreg * a.nchunks) return;
+  const int reg = (int)(logical % a.nreg);
+  const int g0 = (int)(logical / a.nreg) * a.gpc;
+  const int g1 = min(a.ngroups, g0 + a.gpc);
+  if (g0 >= g1) return;
+  const int tid = threadIdx.x;
   const int p0 = a.reg_pt[reg], np = a.reg_pt[reg + 1] - p0;
   const int s0 = a.reg_slot[reg], nslot = a.reg_slot[reg + 1] - s0;
-  if (SCATTER) {  // the coefficients of the region's projectors for the block's orbitals
-    for (int it = threadIdx.x; it < nslot * G; it += 256) {
-      const int ls = it / G, u = it % G;
-      as[it] = u < nv ? a.alpha[(int64_t)a.slot_q[s0 + ls] * a.ns + v0 + u] : TC(0);
+  // the region's tables
+  const int eb = a.pt_ent[p0];
+  if (SCATTER) {
+    const int ne = a.pt_ent[p0 + np] - eb;
+    for (int e = tid; e < ne; e += kBandThreads) {
+      echi[e] = a.ent_chi[eb + e];
+      els[e] = (unsigned short)a.ent_ls[eb + e];
     }
-    __syncthreads();
   }
-  // the region's points: final values (after the scatter) to LDS
-  for (int p = threadIdx.x; p < np; p += 256) {
-    const int64_t i = a.pt_idx[p0 + p];
-    TC y[G];
-#pragma unroll
-    for (int u = 0; u < G; ++u) y[u] = u < nv ? TC(a.y[(int64_t)(v0 + u) * a.nd + i]) : TC(0);
-    if (SCATTER) {
-      TC t[G];
-#pragma unroll
-      for (int u = 0; u < G; ++u) t[u] = TC(0);
-      const int e0 = a.pt_ent[p0 + p], e1 = a.pt_ent[p0 + p + 1];
-      for (int e = e0; e < e1; ++e) {
-        const TC c = a.ent_chi[e];
-        const TC* al = as + a.ent_ls[e] * G;
-#pragma unroll
-        for (int u = 0; u < G; ++u) t[u] += c * al[u];
-      }
-#pragma unroll
-      for (int u = 0; u < G; ++u) {
-        if (u >= nv) break;
-        y[u] += a.sa * t[u];
-        a.y[(int64_t)(v0 + u) * a.nd + i] = TY(y[u]);
-        y[u] = TC(TY(y[u]));  // the gather reads the stored value
-      }
+  const int gb = a.slot_ent[s0];
+  if (gather) {
+    const int ne = a.slot_ent[s0 + nslot] - gb;
+    for (int e = tid; e < ne; e += kBandThreads) {
+      gchi[e] = a.gent_chi[gb + e];
+      gloc[e] = (unsigned short)a.gent_loc[gb + e];
     }
-#pragma unroll
-    for (int u = 0; u < G; ++u) ys[p * G + u] = y[u];
   }
-  if (!gather) return;
+  for (int sl = tid; sl <= nslot; sl += kBandThreads) sent[sl] = a.slot_ent[s0 + sl] - gb;
+  for (int sl = tid; sl < nslot; sl += kBandThreads) sq[sl] = a.slot_q[s0 + sl];
+  const bool own = tid < np;
+  int64_t pi = 0;
+  int e0 = 0, e1 = 0;
+  if (own) {
+    pi = a.pt_idx[p0 + tid];
+    e0 = a.pt_ent[p0 + tid] - eb;
+    e1 = a.pt_ent[p0 + tid + 1] - eb;
+  }
+  const int nitem = nslot * G;
+  auto load_y = [&](int g, TC (&y)[G]) {
+    const int v0 = g * G;
+#pragma unroll
+    for (int u = 0; u < G; ++u) y[u] = own && v0 + u < a.ns ? TC(a.y[(int64_t)(v0 + u) * a.nd + pi]) : TC(0);
+  };
+  auto load_alpha = [&](int g, TC (&an)[AJ]) {
+    const int v0 = g * G;
+#pragma unroll
+    for (int j = 0; j < AJ; ++j) {
+      const int it = tid + j * kBandThreads, ls = it / G, u = it % G;
+      an[j] = it < nitem && v0 + u < a.ns ? a.alpha[(int64_t)sq[ls] * a.ns + v0 + u] : TC(0);
+    }
+  };
+  auto stage_alpha = [&](const TC (&an)[AJ]) {
+#pragma unroll
+    for (int j = 0; j < AJ; ++j) {
+      const int it = tid + j * kBandThreads;
+      if (it < nitem) as[it] = an[j];
+    }
+  };
+  __syncthreads();  // slot columns staged
+  TC yc[G], yn[G], an[AJ];
+  load_y(g0, yc);
+  if (SCATTER) {
+    load_alpha(g0, an);
+    stage_alpha(an);
+  }
   __syncthreads();
-  // slot partials: one thread per (slot, orbital), the slot's entries summed in index order
-  // (entries fetched eight at a time so their loads overlap)
-  for (int it = threadIdx.x; it < nslot * G; it += 256) {
-    const int sl = s0 + it / G, u = it % G;
-    if (u >= nv) continue;
-    TC sum = TC(0);
-    int e = a.slot_ent[sl];
-    const int e1 = a.slot_ent[sl + 1];
-    for (; e + 8 <= e1; e += 8) {
-      int l[8];
-      TC c[8];
+  for (int g = g0; g < g1; ++g) {
+    const int v0 = g * G, nv = min(G, a.ns - v0);
+    const bool more = g + 1 < g1;
+    if (more) {
+      load_y(g + 1, yn);
+      if (SCATTER) load_alpha(g + 1, an);
+    }
+    if (own) {
+      TC y[G];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        l[k] = a.gent_loc[e + k];
-        c[k] = a.gent_chi[e + k];
+      for (int u = 0; u < G; ++u) y[u] = yc[u];
+      if (SCATTER) {
+        TC t[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) t[u] = TC(0);
+        for (int e = e0; e < e1; ++e) {
+          const TC c = echi[e];
+          const TC* al = as + els[e] * G;
+#pragma unroll
+          for (int u = 0; u < G; ++u) t[u] += c * al[u];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          if (u >= nv) break;
+          y[u] += a.sa * t[u];
+          a.y[(int64_t)(v0 + u) * a.nd + pi] = TY(y[u]);
+          y[u] = TC(TY(y[u]));  // the gather reads the stored value
+        }
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sum += c[k] * ys[l[k] * G + u];
+      for (int u = 0; u < G; ++u) ys[tid * G + u] = y[u];
     }
-    for (; e < e1; ++e) sum += a.gent_chi[e] * ys[a.gent_loc[e] * G + u];
-    a.partial[(int64_t)sl * a.ns + v0 + u] = sum;
+    __syncthreads();  // ys complete; the staged coefficients are no longer read
+    if (SCATTER && more) stage_alpha(an);
+    if (gather) {
+      // slot partials: one thread per (slot, orbital), the slot's entries in index order
+      for (int it = tid; it < nitem; it += kBandThreads) {
+        const int sl = it / G, u = it % G;
+        if (u >= nv) continue;
+        TC sum = TC(0);
+        for (int e = sent[sl]; e < sent[sl + 1]; ++e) sum += gchi[e] * ys[gloc[e] * G + u];
+        a.partial[(int64_t)(s0 + sl) * a.ns + v0 + u] = sum;
+      }
+    }
+    __syncthreads();  // ys free, next coefficients staged
+#pragma unroll
+    for (int u = 0; u < G; ++u) yc[u] = yn[u];
   }
 }
 
@@ -233,13 +290,18 @@ hipError_t launch_nl_band(const NbArgs<TY, TC>& a0, bool scatter, bool gather, h
   NbArgs<TY, TC> a = a0;
   constexpr int G = band_g<TC>();
   a.ngroups = (a.ns + G - 1) / G;
-  const int64_t nb = (int64_t)a.nreg * a.ngroups;
+  // runs of groups: about 4096 blocks in all (16 per CU at two resident per CU), each run
+  // as long as that allows (the tables are staged once per run)
+  const int want = (int)std::min<int64_t>(a.ngroups, std::max<int64_t>(1, (4096 + a.nreg - 1) / a.nreg));
+  a.gpc = (a.ngroups + want - 1) / want;
+  a.nchunks = (a.ngroups + a.gpc - 1) / a.gpc;
+  const int64_t nb = (int64_t)a.nreg * a.nchunks;
   a.per_xcd = (int)((nb + 7) / 8);
   const dim3 grid((unsigned)(a.per_xcd * 8));
   if (scatter)
-    hipLaunchKernelGGL((nl_band_kernel<TY, TC, true>), grid, dim3(256), 0, s, a, gather ? 1 : 0);
+    hipLaunchKernelGGL((nl_band_kernel<TY, TC, true>), grid, dim3(kBandThreads), 0, s, a, gather ? 1 : 0);
   else
-    hipLaunchKernelGGL((nl_band_kernel<TY, TC, false>), grid, dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL((nl_band_kernel<TY, TC, false>), grid, dim3(kBandThreads), 0, s, a, 1);
   return hipGetLastError();
 }
 
