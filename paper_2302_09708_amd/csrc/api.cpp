@@ -1153,74 +1153,96 @@ void free_band_tables(chefsi_handle* h) {
   h->nb_reg = h->nb_pts = h->nb_slots = 0;
 }
 
-// Band-pass tables from the point-major projector table: regions of consecutive touched
-// points (grid index order), each closed before it would exceed kBandMaxPts points,
-// kBandMaxSlots projectors or kBandMaxEnt entries; each region lists its points with their
-// entries, and its projector slots (projector order) with their entries (point order);
-// each projector lists its slots (region order) for the reduction.
-void build_band_tables(chefsi_handle* h) {
-  free_band_tables(h);
-  const std::vector<int>& cnt = h->pt_cnt;
-  std::vector<int> reg_pt(1, 0), pt_idx, pt_ent(1, 0), ent_q, ent_ls, reg_slot(1, 0), slot_ent(1, 0), gent_loc,
-      slot_q;
-  std::vector<double> ent_chi, gent_chi;
-  std::vector<std::vector<int>> q_slots(h->np_tot);
-  std::vector<int64_t> open;           // points of the open region
-  std::vector<int> stamp(h->np_tot, -1);  // region that last counted each projector
+// Band-pass regions from a point-major projector table (cnt: nd + 1 entry offsets, col: the
+// projector column of every entry): regions of consecutive touched points (grid index
+// order), each closed before it would exceed kBandMaxPts points, kBandMaxSlots projectors or
+// max_ent entries; each region lists its points with their entries, and its projector slots
+// (projector order) with their entries (point order); each projector lists its slots (region
+// order) for the reduction.  ent_src / gent_src name the table entry behind every scatter /
+// gather entry, so the caller attaches values of its own type.
+struct BandRegions {
+  std::vector<int> reg_pt{0}, pt_idx, pt_ent{0}, ent_ls, reg_slot{0}, slot_q, slot_ent{0}, gent_loc, q_slot_ptr{0},
+      q_slot, ent_src, gent_src;
+};
+
+BandRegions band_regions(int64_t nd, const int* cnt, const int* col, int np_tot, int max_ent) {
+  BandRegions R;
+  std::vector<std::vector<int>> q_slots(np_tot);
+  std::vector<int64_t> open;              // points of the open region
+  std::vector<int> stamp(np_tot, -1);     // region that last counted each projector
   int nreg = 0, open_ent = 0, open_q = 0;
   auto close_region = [&]() {
-    const int first = (int)pt_idx.size();
-    std::map<int, std::vector<std::pair<int, double>>> slots;  // projector -> (local point, chi)
+    const int first = (int)R.pt_idx.size();
+    std::map<int, std::vector<std::pair<int, int>>> slots;  // projector -> (local point, table entry)
+    const size_t e_first = R.ent_src.size();
     for (int64_t i : open) {
-      const int loc = (int)pt_idx.size() - first;
-      pt_idx.push_back((int)i);
+      const int loc = (int)R.pt_idx.size() - first;
+      R.pt_idx.push_back((int)i);
       for (int e = cnt[i]; e < cnt[i + 1]; ++e) {
-        ent_q.push_back(h->pt_col[e]);
-        ent_chi.push_back(h->pt_val[e]);
-        slots[h->pt_col[e]].emplace_back(loc, h->pt_val[e]);
+        R.ent_src.push_back(e);
+        slots[col[e]].emplace_back(loc, e);
       }
-      pt_ent.push_back((int)ent_q.size());
+      R.pt_ent.push_back((int)R.ent_src.size());
     }
-    reg_pt.push_back((int)pt_idx.size());
+    R.reg_pt.push_back((int)R.pt_idx.size());
     std::map<int, int> local;  // region slot of every entry (slots in projector order)
     for (auto& kv : slots) local.emplace(kv.first, (int)local.size());
-    for (size_t e = ent_ls.size(); e < ent_q.size(); ++e) ent_ls.push_back(local.at(ent_q[e]));
+    for (size_t e = e_first; e < R.ent_src.size(); ++e) R.ent_ls.push_back(local.at(col[R.ent_src[e]]));
     for (auto& kv : slots) {
-      q_slots[kv.first].push_back((int)slot_q.size());
-      slot_q.push_back(kv.first);
+      q_slots[kv.first].push_back((int)R.slot_q.size());
+      R.slot_q.push_back(kv.first);
       for (auto& pe : kv.second) {
-        gent_loc.push_back(pe.first);
-        gent_chi.push_back(pe.second);
+        R.gent_loc.push_back(pe.first);
+        R.gent_src.push_back(pe.second);
       }
-      slot_ent.push_back((int)gent_loc.size());
+      R.slot_ent.push_back((int)R.gent_loc.size());
     }
-    reg_slot.push_back((int)slot_q.size());
+    R.reg_slot.push_back((int)R.slot_q.size());
     open.clear();
     open_ent = open_q = 0;
     ++nreg;
   };
-  for (int64_t i = 0; i < h->nd; ++i) {
+  for (int64_t i = 0; i < nd; ++i) {
     const int n = cnt[i + 1] - cnt[i];
     if (n == 0) continue;
-    check(n <= kBandMaxSlots, "a grid point lies in too many projector supports for the band pass");
+    check(n <= kBandMaxSlots && n <= max_ent, "a grid point lies in too many projector supports for the band pass");
     int fresh = 0;
-    for (int e = cnt[i]; e < cnt[i + 1]; ++e) fresh += stamp[h->pt_col[e]] != nreg;
-    if (!open.empty() && ((int)open.size() + 1 > kBandMaxPts || open_ent + n > kBandMaxEnt ||
-                          open_q + fresh > kBandMaxSlots)) {
+    for (int e = cnt[i]; e < cnt[i + 1]; ++e) fresh += stamp[col[e]] != nreg;
+    if (!open.empty() &&
+        ((int)open.size() + 1 > kBandMaxPts || open_ent + n > max_ent || open_q + fresh > kBandMaxSlots)) {
       close_region();
       fresh = n;  // every projector of the point is new to the next region
     }
-    for (int e = cnt[i]; e < cnt[i + 1]; ++e) stamp[h->pt_col[e]] = nreg;
+    for (int e = cnt[i]; e < cnt[i + 1]; ++e) stamp[col[e]] = nreg;
     open.push_back(i);
     open_ent += n;
     open_q += fresh;
   }
   if (!open.empty()) close_region();
-  std::vector<int> q_slot_ptr(1, 0), q_slot;
-  for (int q = 0; q < h->np_tot; ++q) {
-    for (int sl : q_slots[q]) q_slot.push_back(sl);
-    q_slot_ptr.push_back((int)q_slot.size());
+  for (int q = 0; q < np_tot; ++q) {
+    for (int sl : q_slots[q]) R.q_slot.push_back(sl);
+    R.q_slot_ptr.push_back((int)R.q_slot.size());
   }
+  return R;
+}
+
+// Band-pass tables of a real handle (FP64 and FP32 copies of the projector values).
+void build_band_tables(chefsi_handle* h) {
+  free_band_tables(h);
+  BandRegions R = band_regions(h->nd, h->pt_cnt.data(), h->pt_col.data(), h->np_tot, kBandMaxEnt);
+  std::vector<double> ent_chi(R.ent_src.size()), gent_chi(R.gent_src.size());
+  for (size_t e = 0; e < ent_chi.size(); ++e) ent_chi[e] = h->pt_val[R.ent_src[e]];
+  for (size_t e = 0; e < gent_chi.size(); ++e) gent_chi[e] = h->pt_val[R.gent_src[e]];
+  const std::vector<int>& reg_pt = R.reg_pt;
+  const std::vector<int>& pt_idx = R.pt_idx;
+  const std::vector<int>& pt_ent = R.pt_ent;
+  const std::vector<int>& ent_ls = R.ent_ls;
+  const std::vector<int>& slot_q = R.slot_q;
+  const std::vector<int>& reg_slot = R.reg_slot;
+  const std::vector<int>& slot_ent = R.slot_ent;
+  const std::vector<int>& gent_loc = R.gent_loc;
+  const std::vector<int>& q_slot_ptr = R.q_slot_ptr;
+  const std::vector<int>& q_slot = R.q_slot;
   const size_t before = h->device_bytes;
   try {
     h->nb_reg_pt = upload(h, reg_pt.data(), reg_pt.size());
@@ -2439,12 +2461,12 @@ struct chefsi_kpoint {
   std::vector<double> w;
   int n_atoms = 0, np_tot = 0, n_pts = 0;
   double* veff = nullptr;
-  int *supp_off = nullptr, *supp_idx = nullptr, *nproj = nullptr, *poff = nullptr;
-  int64_t* chi_off = nullptr;
-  double2* chi = nullptr;
   double* gdv = nullptr;
-  int *pt = nullptr, *ptr = nullptr, *col = nullptr;
-  double2* val = nullptr;
+  // band-pass tables (regions of touched points, complex chi~; the gather table conjugated)
+  int nreg = 0;
+  int *reg_pt = nullptr, *pt_idx = nullptr, *pt_ent = nullptr, *ent_ls = nullptr, *reg_slot = nullptr,
+      *slot_q = nullptr, *slot_ent = nullptr, *gent_loc = nullptr, *q_slot_ptr = nullptr, *q_slot = nullptr;
+  double2 *ent_chi = nullptr, *gent_chi = nullptr, *partial = nullptr;
   double* pinned = nullptr;
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
@@ -2552,32 +2574,45 @@ T* kupload(const T* src, size_t n) {
 }
 
 void krelease(chefsi_kpoint* h) {
-  void* ptrs[] = {h->veff, h->supp_off, h->supp_idx, h->nproj, h->poff, h->chi_off, h->chi, h->gdv,
-                  h->pt,   h->ptr,      h->col,      h->val};
+  void* ptrs[] = {h->veff,     h->gdv,      h->reg_pt,   h->pt_idx,     h->pt_ent,   h->ent_ls, h->reg_slot,
+                  h->slot_q,   h->slot_ent, h->gent_loc, h->q_slot_ptr, h->q_slot,   h->ent_chi, h->gent_chi,
+                  h->partial};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->blas) rocblas_destroy_handle(h->blas);
 }
 
-// out = sa ((H_k x) - sc x) + sb prev: projector gather, stencil + Veff + recurrence, scatter.
+ZNbArgs zband_args(const chefsi_kpoint* h, double2* y, int ns, const double2* alpha, double sa) {
+  ZNbArgs b{};
+  b.y = y;
+  b.nd = h->nd;
+  b.ns = ns;
+  b.nreg = h->nreg;
+  b.reg_pt = h->reg_pt;
+  b.pt_idx = h->pt_idx;
+  b.pt_ent = h->pt_ent;
+  b.ent_ls = h->ent_ls;
+  b.ent_chi = h->ent_chi;
+  b.reg_slot = h->reg_slot;
+  b.slot_q = h->slot_q;
+  b.slot_ent = h->slot_ent;
+  b.gent_loc = h->gent_loc;
+  b.gent_chi = h->gent_chi;
+  b.alpha = alpha;
+  b.sa = sa;
+  b.partial = h->partial;
+  return b;
+}
+
+// out = sa ((H_k x) - sc x) + sb prev: stencil + Veff + recurrence, then the band pass adds
+// sa V_nl x at the touched points (coefficients alpha of x: formed first by a gather-only
+// pass unless alpha_ready) and, when want_next, leaves the coefficients of out in alpha.
 void zapply(chefsi_kpoint* h, const double2* x, const double2* prev, double2* out, int ns, double sa, double sc,
-            double sb, double2* alpha, hipStream_t s) {
-  if (h->np_tot > 0) {
-    ZNlArgs g{};
-    g.x = x;
-    g.nd = h->nd;
-    g.n_atoms = h->n_atoms;
-    g.supp_off = h->supp_off;
-    g.supp_idx = h->supp_idx;
-    g.chi_off = h->chi_off;
-    g.nproj = h->nproj;
-    g.poff = h->poff;
-    g.chi = h->chi;
-    g.gdv = h->gdv;
-    g.alpha = alpha;
-    g.np_tot = h->np_tot;
-    HIP_TRY(launch_zproject(g, ns, s));
+            double sb, double2* alpha, hipStream_t s, bool alpha_ready = false, bool want_next = false) {
+  if (h->np_tot > 0 && !alpha_ready) {
+    HIP_TRY(launch_zband(zband_args(h, const_cast<double2*>(x), ns, alpha, 0.0), false, true, s));
+    HIP_TRY(launch_zband_reduce(h->partial, h->q_slot_ptr, h->q_slot, h->gdv, h->np_tot, ns, alpha, s));
   }
   ZHxArgs a{};
   a.x = x;
@@ -2600,19 +2635,10 @@ void zapply(chefsi_kpoint* h, const double2* x, const double2* prev, double2* ou
   a.sc = sc;
   a.sb = sb;
   HIP_TRY(launch_zhx(a, ns, s));
-  if (h->n_pts > 0) {
-    ZNsArgs n{};
-    n.out = out;
-    n.nd = h->nd;
-    n.n_pts = h->n_pts;
-    n.pt = h->pt;
-    n.ptr = h->ptr;
-    n.col = h->col;
-    n.val = h->val;
-    n.alpha = alpha;
-    n.np_tot = h->np_tot;
-    n.sa = sa;
-    HIP_TRY(launch_zscatter(n, ns, s));
+  if (h->np_tot > 0) {
+    HIP_TRY(launch_zband(zband_args(h, out, ns, alpha, sa), true, want_next, s));
+    if (want_next)
+      HIP_TRY(launch_zband_reduce(h->partial, h->q_slot_ptr, h->q_slot, h->gdv, h->np_tot, ns, alpha, s));
   }
 }
 
@@ -2692,7 +2718,7 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
     std::vector<double> veff(veff_host, veff_host + nd);
     for (double v : veff) check(std::isfinite(v), "Veff must be finite");
 
-    std::vector<int> soff, sidx, nproj, poff, pts, ptr, cols;
+    std::vector<int> soff, sidx, nproj, poff, cnt, cols;
     std::vector<int64_t> coff;
     std::vector<double2> chi, vals;
     std::vector<double> gdv;
@@ -2750,8 +2776,8 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
         check(std::isfinite(nl->gamma[q]), "gamma must be finite");
         gdv[q] = nl->gamma[q] * dv;
       }
-      // point-major entries for the scatter: grid points in increasing order, atoms in order
-      std::vector<int> cnt(nd + 1, 0);
+      // point-major entries: grid points in increasing order, atoms in order
+      cnt.assign(nd + 1, 0);
       for (int J = 0; J < na; ++J)
         for (int64_t s = nl->supp_ptr[J]; s < nl->supp_ptr[J + 1]; ++s) cnt[sidx[s] + 1] += nproj[J];
       for (int64_t i = 0; i < nd; ++i) cnt[i + 1] += cnt[i];
@@ -2770,13 +2796,7 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
           }
         }
       }
-      ptr.push_back(0);
-      for (int64_t i = 0; i < nd; ++i)
-        if (cnt[i + 1] > cnt[i]) {
-          pts.push_back((int)i);
-          ptr.push_back(cnt[i + 1]);
-        }
-      h->n_pts = (int)pts.size();
+      check(nent < ((int64_t)1 << 31), "too many projector entries");
     }
 
     HIP_TRY(hipGetDevice(&h->device));
@@ -2788,17 +2808,34 @@ int chefsi_kpoint_create(const chefsi_grid_t* grid, const double* veff_host, con
     }
     h->veff = kupload(veff.data(), veff.size());
     if (h->np_tot > 0) {
-      h->supp_off = kupload(soff.data(), soff.size());
-      h->supp_idx = kupload(sidx.data(), sidx.size());
-      h->nproj = kupload(nproj.data(), nproj.size());
-      h->poff = kupload(poff.data(), poff.size());
-      h->chi_off = kupload(coff.data(), coff.size());
-      h->chi = kupload(chi.data(), chi.size());
+      // band-pass regions of the touched points (the real path's tables with chi~ values)
+      const BandRegions R = band_regions(nd, cnt.data(), cols.data(), h->np_tot, kZBandMaxEnt);
+      std::vector<double2> ent_chi(R.ent_src.size()), gent_chi(R.gent_src.size());
+      for (size_t e = 0; e < ent_chi.size(); ++e) ent_chi[e] = vals[R.ent_src[e]];
+      for (size_t e = 0; e < gent_chi.size(); ++e) {
+        const double2 v = vals[R.gent_src[e]];
+        gent_chi[e] = make_double2(v.x, -v.y);
+      }
+      h->nreg = (int)R.reg_pt.size() - 1;
+      h->n_pts = (int)R.pt_idx.size();
       h->gdv = kupload(gdv.data(), gdv.size());
-      h->pt = kupload(pts.data(), pts.size());
-      h->ptr = kupload(ptr.data(), ptr.size());
-      h->col = kupload(cols.data(), cols.size());
-      h->val = kupload(vals.data(), vals.size());
+      h->reg_pt = kupload(R.reg_pt.data(), R.reg_pt.size());
+      h->pt_idx = kupload(R.pt_idx.data(), R.pt_idx.size());
+      h->pt_ent = kupload(R.pt_ent.data(), R.pt_ent.size());
+      h->ent_ls = kupload(R.ent_ls.data(), R.ent_ls.size());
+      h->ent_chi = kupload(ent_chi.data(), ent_chi.size());
+      h->reg_slot = kupload(R.reg_slot.data(), R.reg_slot.size());
+      h->slot_q = kupload(R.slot_q.data(), R.slot_q.size());
+      h->slot_ent = kupload(R.slot_ent.data(), R.slot_ent.size());
+      h->gent_loc = kupload(R.gent_loc.data(), R.gent_loc.size());
+      h->gent_chi = kupload(gent_chi.data(), gent_chi.size());
+      h->q_slot_ptr = kupload(R.q_slot_ptr.data(), R.q_slot_ptr.size());
+      h->q_slot = kupload(R.q_slot.data(), R.q_slot.size());
+      if (hipMalloc((void**)&h->partial, std::max<size_t>(1, R.slot_q.size()) * (size_t)max_ns * sizeof(double2)) !=
+          hipSuccess) {
+        h->partial = nullptr;
+        throw Error{CHEFSI_ERR_OOM, "device allocation failed (band-pass partial sums)"};
+      }
     }
     *out = h;
     return CHEFSI_OK;
@@ -2863,18 +2900,20 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
     const double e = 0.5 * (lam_hi - lam_cut);
     const double s1 = e / (lam_lo - c);
     double sig = s1;
-    zapply(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s);
+    // the projector coefficients of each output are left by its band pass for the next
+    // application
+    zapply(h, A, nullptr, B, ns, s1 / e, c, 0.0, alpha, s, false, true);
     double2* cur = B;
     double2* other = A;
     for (int k = 1; k < degree; ++k) {
       const double sig_next = 1.0 / (2.0 / s1 - sig);
-      zapply(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s);
+      zapply(h, cur, other, other, ns, 2.0 * sig_next / e, c, -sig * sig_next, alpha, s, true, true);
       std::swap(cur, other);
       sig = sig_next;
     }
     double2* Xf = cur;
     double2* Yf = other;
-    zapply(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s);  // Y~ = H X~
+    zapply(h, Xf, nullptr, Yf, ns, 1.0, 0.0, 0.0, alpha, s, true, false);  // Y~ = H X~
     // projection (upper triangles made Hermitian)
     const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
     const rocblas_int ld = (rocblas_int)h->nd;

@@ -356,37 +356,34 @@ struct ZTiling {
 };
 ZTiling plan_zhx(int nx, int ny, int nz, int ns, int radius);
 
-struct ZNlArgs {
-  const double2* x;
+// complex band pass (the real band pass's regions and tables with chi~ values; the gather
+// table holds conj(chi~)); alpha projector-major: alpha[q * ns + v]
+constexpr int kZBandMaxEnt = 1024;  // projector entries of one region (complex tables in LDS)
+struct ZNbArgs {
+  double2* y;  // Nd x ns block (ld nd): scattered in place when scatter, read otherwise
   int64_t nd;
-  int n_atoms;
-  const int* supp_off;     // n_atoms + 1
-  const int* supp_idx;
-  const int64_t* chi_off;  // n_atoms, offset of chi~_J (n_J x np_J, column major)
-  const int* nproj;
-  const int* poff;
-  const double2* chi;      // Bloch-phased projector values
-  const double* gdv;       // gamma * dV per projector column
-  double2* alpha;          // ns x np_tot, projector column fastest
-  int np_tot;
-};
-
-struct ZNsArgs {
-  double2* out;
-  int64_t nd;
-  int n_pts;
-  const int* pt;      // n_pts grid points
-  const int* ptr;     // n_pts + 1 entry offsets
-  const int* col;     // projector column of every entry
-  const double2* val; // chi~ of every entry
+  int ns;
+  int nreg;
+  const int* reg_pt;
+  const int* pt_idx;
+  const int* pt_ent;
+  const int* ent_ls;
+  const double2* ent_chi;
+  const int* reg_slot;
+  const int* slot_q;
+  const int* slot_ent;
+  const int* gent_loc;
+  const double2* gent_chi;
   const double2* alpha;
-  int np_tot;
   double sa;
+  double2* partial;  // nslots x ns, slot major
+  int ngroups, gpc, nchunks, per_xcd;  // set by the launcher
 };
 
 hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s);
-hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s);
-hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s);
+hipError_t launch_zband(const ZNbArgs& a, bool scatter, bool gather, hipStream_t s);
+hipError_t launch_zband_reduce(const double2* partial, const int* q_slot_ptr, const int* q_slot, const double* gdv,
+                               int np_tot, int ns, double2* alpha, hipStream_t s);
 // C = Hermitian completion of sum_q P_q (upper triangles read, fixed order), P: nparts
 // column-major ns x ns complex partial products.
 hipError_t launch_zsum_partials(const double2* P, int nparts, int ns, double2* C, hipStream_t s);

@@ -1,9 +1,12 @@
 // H at a Bloch wavevector k on complex FP64 orbitals (interleaved re/im, Nd x Ns column
 // major): Sec. 2 of the paper runs every Brillouin-zone sample other than Gamma in complex
-// double precision.  Three kernels, launched in this order on one stream:
-//   zproject  alpha[v, q] = gamma_q dV sum_{s in S_J} conj(chi~_J[s, a]) x[v, S_J[s]]
+// double precision.  Kernels, launched in this order on one stream:
 //   zhx       out = sa ((T_k + Veff) x - sc x) + sb prev    (Bloch-phased FD ghosts)
-//   zscatter  out[v, p] += sa sum_{e in entries of p} chi~[e] alpha[v, col[e]]
+//   zband     out[v, p] += sa sum_{e in entries of p} chi~[e] alpha[col[e], v] at every
+//             touched point p, then the slot partials of the next coefficients,
+//             sum over the region's points of q of conj(chi~) out[v, p]
+//   zband_reduce  alpha[q, v] = gamma_q dV * (sum of q's slot partials, region order)
+// (a gather-only zband pass forms the coefficients of a block that no pass has produced).
 // chi~ carries the Bloch phase of the image each support point belongs to (set on the
 // host); the three-term filter recurrence uses the same real scalars as the real path.
 // Every sum runs in a fixed order: results are bitwise reproducible.
@@ -17,9 +20,6 @@ namespace {
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -228,93 +228,184 @@ __global__ __launch_bounds__(kZMaxThreads) void zhx_kernel(ZHxArgs a, ZTiling t)
   }
 }
 
-constexpr int kZThreads = 256;
+// ---------------------------------------------------------------------------
+// zband: the complex counterpart of the real band pass.  One block per (region, run of
+// orbital groups of kZG orbitals), one thread per point; the region's entry tables sit in
+// LDS for the whole run; the next group's point values and staged coefficients are fetched
+// into registers while the current group is scattered and gathered.
+// ---------------------------------------------------------------------------
+constexpr int kZG = 4;  // orbitals per group: 512 points x 4 x 16 B = 32 KB of LDS
 
-constexpr int kZProj = 4;  // projectors of an atom summed per pass over its support
-
-// one block per (atom, orbital); every thread sums its strided share of the support for
-// up to four projectors at once (each support value read once per four projectors), then
-// a fixed-shape tree sums the threads
-__global__ __launch_bounds__(kZThreads) void zproject_kernel(ZNlArgs a) {
-  __shared__ double2 red[kZProj][kZThreads];
-  const int J = blockIdx.x;
-  const int64_t v = blockIdx.y;
-  const int s0 = a.supp_off[J], nj = a.supp_off[J + 1] - s0;
-  const int npj = a.nproj[J];
-  const int64_t co = a.chi_off[J];
-  const double2* __restrict__ xv = a.x + v * a.nd;
-  for (int q0 = 0; q0 < npj; q0 += kZProj) {
-    const int nq = min(kZProj, npj - q0);
-    double2 acc[kZProj];
+template <bool SCATTER>
+__global__ __launch_bounds__(kBandThreads) void zband_kernel(ZNbArgs a, int gather) {
+  constexpr int AJ = (kBandMaxSlots * kZG + kBandThreads - 1) / kBandThreads;
+  __shared__ double2 ys[kBandMaxPts * kZG];
+  __shared__ double2 as[kBandMaxSlots * kZG];
+  __shared__ double2 echi[kZBandMaxEnt];
+  __shared__ double2 gchi[kZBandMaxEnt];
+  __shared__ unsigned short els[kZBandMaxEnt];
+  __shared__ unsigned short gloc[kZBandMaxEnt];
+  __shared__ int sent[kBandMaxSlots + 1];
+  __shared__ int sq[kBandMaxSlots];
+  const int64_t logical = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+  if (logical >= (int64_t)a.nreg * a.nchunks) return;
+  const int reg = (int)(logical / a.nchunks);
+  const int g0 = (int)(logical % a.nchunks) * a.gpc;
+  const int g1 = min(a.ngroups, g0 + a.gpc);
+  if (g0 >= g1) return;
+  const int tid = threadIdx.x;
+  const int p0 = a.reg_pt[reg], np = a.reg_pt[reg + 1] - p0;
+  const int s0 = a.reg_slot[reg], nslot = a.reg_slot[reg + 1] - s0;
+  const int eb = a.pt_ent[p0];
+  if (SCATTER) {
+    const int ne = a.pt_ent[p0 + np] - eb;
+    for (int e = tid; e < ne; e += kBandThreads) {
+      echi[e] = a.ent_chi[eb + e];
+      els[e] = (unsigned short)a.ent_ls[eb + e];
+    }
+  }
+  const int gb = a.slot_ent[s0];
+  if (gather) {
+    const int ne = a.slot_ent[s0 + nslot] - gb;
+    for (int e = tid; e < ne; e += kBandThreads) {
+      gchi[e] = a.gent_chi[gb + e];
+      gloc[e] = (unsigned short)a.gent_loc[gb + e];
+    }
+  }
+  for (int sl = tid; sl <= nslot; sl += kBandThreads) sent[sl] = a.slot_ent[s0 + sl] - gb;
+  for (int sl = tid; sl < nslot; sl += kBandThreads) sq[sl] = a.slot_q[s0 + sl];
+  const bool own = tid < np;
+  int64_t pi = 0;
+  int e0 = 0, e1 = 0;
+  if (own) {
+    pi = a.pt_idx[p0 + tid];
+    e0 = a.pt_ent[p0 + tid] - eb;
+    e1 = a.pt_ent[p0 + tid + 1] - eb;
+  }
+  const int nitem = nslot * kZG;
+  // register values as separate real and imaginary arrays (kept in registers)
+  auto load_y = [&](int g, double (&yr)[kZG], double (&yi)[kZG]) {
+    const int v0 = g * kZG;
 #pragma unroll
-    for (int u = 0; u < kZProj; ++u) acc[u] = make_double2(0.0, 0.0);
-    for (int s = threadIdx.x; s < nj; s += kZThreads) {
-      const double2 xs = xv[a.supp_idx[s0 + s]];
+    for (int u = 0; u < kZG; ++u) {
+      double2 v = make_double2(0.0, 0.0);
+      if (own && v0 + u < a.ns) v = a.y[(int64_t)(v0 + u) * a.nd + pi];
+      yr[u] = v.x;
+      yi[u] = v.y;
+    }
+  };
+  auto load_alpha = [&](int g, double (&ar)[AJ], double (&ai)[AJ]) {
+    const int v0 = g * kZG;
 #pragma unroll
-      for (int u = 0; u < kZProj; ++u) {
-        if (u < nq) {
-          const double2 t = cmulc(a.chi[co + (int64_t)(q0 + u) * nj + s], xs);
-          acc[u].x += t.x;
-          acc[u].y += t.y;
+    for (int j = 0; j < AJ; ++j) {
+      const int it = tid + j * kBandThreads, ls = it / kZG, u = it % kZG;
+      double2 v = make_double2(0.0, 0.0);
+      if (it < nitem && v0 + u < a.ns) v = a.alpha[(int64_t)sq[ls] * a.ns + v0 + u];
+      ar[j] = v.x;
+      ai[j] = v.y;
+    }
+  };
+  auto stage_alpha = [&](const double (&ar)[AJ], const double (&ai)[AJ]) {
+#pragma unroll
+    for (int j = 0; j < AJ; ++j) {
+      const int it = tid + j * kBandThreads;
+      if (it < nitem) as[it] = make_double2(ar[j], ai[j]);
+    }
+  };
+  __syncthreads();  // slot columns staged
+  double ycr[kZG], yci[kZG], ynr[kZG], yni[kZG], anr[AJ], ani[AJ];
+  load_y(g0, ycr, yci);
+  if (SCATTER) {
+    load_alpha(g0, anr, ani);
+    stage_alpha(anr, ani);
+  }
+  __syncthreads();
+  for (int g = g0; g < g1; ++g) {
+    const int v0 = g * kZG, nv = min(kZG, a.ns - v0);
+    const bool more = g + 1 < g1;
+    if (more) {
+      load_y(g + 1, ynr, yni);
+      if (SCATTER) load_alpha(g + 1, anr, ani);
+    }
+    if (own) {
+      if (SCATTER) {
+        double tr[kZG], ti[kZG];
+#pragma unroll
+        for (int u = 0; u < kZG; ++u) tr[u] = ti[u] = 0.0;
+        for (int e = e0; e < e1; ++e) {
+          const double2 c = echi[e];
+          const double2* al = as + els[e] * kZG;
+#pragma unroll
+          for (int u = 0; u < kZG; ++u) {
+            const double2 m = cmul(c, al[u]);
+            tr[u] += m.x;
+            ti[u] += m.y;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kZG; ++u) {
+          ycr[u] += a.sa * tr[u];
+          yci[u] += a.sa * ti[u];
+          if (u < nv) a.y[(int64_t)(v0 + u) * a.nd + pi] = make_double2(ycr[u], yci[u]);
         }
       }
+#pragma unroll
+      for (int u = 0; u < kZG; ++u) ys[tid * kZG + u] = make_double2(ycr[u], yci[u]);
     }
+    __syncthreads();  // ys complete; the staged coefficients are no longer read
+    if (SCATTER && more) stage_alpha(anr, ani);
+    if (gather) {
+      // slot partials: one thread per (slot, orbital), the slot's entries in index order
+      for (int it = tid; it < nitem; it += kBandThreads) {
+        const int sl = it / kZG, u = it % kZG;
+        if (u >= nv) continue;
+        // four running sums over entries e = 4 m + c (independent LDS chains), added in a
+        // fixed order
+        double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+        const int eb0 = sent[sl], ee = sent[sl + 1];
+        int e = eb0;
+        for (; e + 4 <= ee; e += 4) {
 #pragma unroll
-    for (int u = 0; u < kZProj; ++u) red[u][threadIdx.x] = acc[u];
-    __syncthreads();
-    for (int w = kZThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-#pragma unroll
-        for (int u = 0; u < kZProj; ++u) {
-          red[u][threadIdx.x].x += red[u][threadIdx.x + w].x;
-          red[u][threadIdx.x].y += red[u][threadIdx.x + w].y;
+          for (int c = 0; c < 4; ++c) {
+            const double2 m = cmul(gchi[e + c], ys[gloc[e + c] * kZG + u]);
+            sr[c] += m.x;
+            si[c] += m.y;
+          }
         }
+        for (int c = 0; e < ee; ++e, ++c) {
+          const double2 m = cmul(gchi[e], ys[gloc[e] * kZG + u]);
+          sr[c] += m.x;
+          si[c] += m.y;
+        }
+        a.partial[(int64_t)(s0 + sl) * a.ns + v0 + u] =
+            make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
       }
-      __syncthreads();
     }
-    if ((int)threadIdx.x < nq) {
-      const int u = threadIdx.x;
-      const int col = a.poff[J] + q0 + u;
-      const double g = a.gdv[col];
-      a.alpha[v * a.np_tot + col] = make_double2(g * red[u][0].x, g * red[u][0].y);
+    __syncthreads();  // ys free, next coefficients staged
+#pragma unroll
+    for (int u = 0; u < kZG; ++u) {
+      ycr[u] = ynr[u];
+      yci[u] = yni[u];
     }
-    __syncthreads();
   }
 }
 
-constexpr int kZScatV = 4;  // orbitals per scatter thread (the point's entries read once)
-
-// one thread per (support point, four orbitals); every output element is written by one thread
-__global__ __launch_bounds__(256) void zscatter_kernel(ZNsArgs a, int ns) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= a.n_pts) return;
-  const int64_t v0 = (int64_t)blockIdx.y * kZScatV;
-  const int nv = (int)min((int64_t)kZScatV, (int64_t)ns - v0);
-  double2 acc[kZScatV];
-#pragma unroll
-  for (int u = 0; u < kZScatV; ++u) acc[u] = make_double2(0.0, 0.0);
-  for (int e = a.ptr[p]; e < a.ptr[p + 1]; ++e) {
-    const double2 c = a.val[e];
-    const int q = a.col[e];
-#pragma unroll
-    for (int u = 0; u < kZScatV; ++u) {
-      if (u < nv) {
-        const double2 t = cmul(c, a.alpha[(v0 + u) * a.np_tot + q]);
-        acc[u].x += t.x;
-        acc[u].y += t.y;
-      }
-    }
+// alpha[q][v] = gdv[q] * sum over the slots of q (region order) of partial[slot][v]
+__global__ __launch_bounds__(256) void zband_reduce_kernel(const double2* __restrict__ partial,
+                                                           const int* __restrict__ q_slot_ptr,
+                                                           const int* __restrict__ q_slot,
+                                                           const double* __restrict__ gdv, int np_tot, int ns,
+                                                           double2* __restrict__ alpha) {
+  const int q = blockIdx.y;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (q >= np_tot || v >= ns) return;
+  double re = 0.0, im = 0.0;
+  for (int k = q_slot_ptr[q]; k < q_slot_ptr[q + 1]; ++k) {
+    const double2 t = partial[(int64_t)q_slot[k] * ns + v];
+    re += t.x;
+    im += t.y;
   }
-#pragma unroll
-  for (int u = 0; u < kZScatV; ++u) {
-    if (u < nv) {
-      double2* o = a.out + (v0 + u) * a.nd + a.pt[p];
-      double2 cur = *o;
-      cur.x += a.sa * acc[u].x;
-      cur.y += a.sa * acc[u].y;
-      *o = cur;
-    }
-  }
+  alpha[(int64_t)q * ns + v] = make_double2(gdv[q] * re, gdv[q] * im);
 }
 
 // C(i, j) = sum_q P_q(i, j) for i <= j in a fixed order (P_q column-major ns x ns), then the
@@ -398,16 +489,29 @@ hipError_t launch_zhx(const ZHxArgs& a, int ns, hipStream_t s) {
   }
 }
 
-hipError_t launch_zproject(const ZNlArgs& a, int ns, hipStream_t s) {
-  if (a.n_atoms <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zproject_kernel, dim3((unsigned)a.n_atoms, (unsigned)ns), dim3(kZThreads), 0, s, a);
+hipError_t launch_zband(const ZNbArgs& a0, bool scatter, bool gather, hipStream_t s) {
+  if (a0.nreg <= 0 || a0.ns <= 0) return hipSuccess;
+  ZNbArgs a = a0;
+  a.ngroups = (a.ns + kZG - 1) / kZG;
+  // runs of groups: about 4096 blocks in all, each run as long as that allows
+  const int want = (int)std::min<int64_t>(a.ngroups, std::max<int64_t>(1, (4096 + a.nreg - 1) / a.nreg));
+  a.gpc = (a.ngroups + want - 1) / want;
+  a.nchunks = (a.ngroups + a.gpc - 1) / a.gpc;
+  const int64_t nb = (int64_t)a.nreg * a.nchunks;
+  a.per_xcd = (int)((nb + 7) / 8);
+  const dim3 grid((unsigned)(a.per_xcd * 8));
+  if (scatter)
+    hipLaunchKernelGGL(zband_kernel<true>, grid, dim3(kBandThreads), 0, s, a, gather ? 1 : 0);
+  else
+    hipLaunchKernelGGL(zband_kernel<false>, grid, dim3(kBandThreads), 0, s, a, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_zscatter(const ZNsArgs& a, int ns, hipStream_t s) {
-  if (a.n_pts <= 0 || ns <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zscatter_kernel, dim3((unsigned)((a.n_pts + 255) / 256), (unsigned)((ns + kZScatV - 1) / kZScatV)),
-                     dim3(256), 0, s, a, ns);
+hipError_t launch_zband_reduce(const double2* partial, const int* q_slot_ptr, const int* q_slot, const double* gdv,
+                               int np_tot, int ns, double2* alpha, hipStream_t s) {
+  if (np_tot <= 0 || ns <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((ns + 255) / 256), (unsigned)np_tot);
+  hipLaunchKernelGGL(zband_reduce_kernel, grid, dim3(256), 0, s, partial, q_slot_ptr, q_slot, gdv, np_tot, ns, alpha);
   return hipGetLastError();
 }
 

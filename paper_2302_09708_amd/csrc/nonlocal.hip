@@ -273,9 +273,17 @@ __global__ __launch_bounds__(kBandThreads) void nl_band_kernel(NbArgs<TY, TC> a,
       for (int it = tid; it < nitem; it += kBandThreads) {
         const int sl = it / G, u = it % G;
         if (u >= nv) continue;
-        TC sum = TC(0);
-        for (int e = sent[sl]; e < sent[sl + 1]; ++e) sum += gchi[e] * ys[gloc[e] * G + u];
-        a.partial[(int64_t)(s0 + sl) * a.ns + v0 + u] = sum;
+        // four running sums over entries e = 4 m + c (independent LDS chains), added in a
+        // fixed order
+        TC s4[4] = {TC(0), TC(0), TC(0), TC(0)};
+        const int eb0 = sent[sl], ee = sent[sl + 1];
+        int e = eb0;
+        for (; e + 4 <= ee; e += 4) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s4[c] += gchi[e + c] * ys[gloc[e + c] * G + u];
+        }
+        for (int c = 0; e < ee; ++e, ++c) s4[c] += gchi[e] * ys[gloc[e] * G + u];
+        a.partial[(int64_t)(s0 + sl) * a.ns + v0 + u] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
     }
     __syncthreads();  // ys free, next coefficients staged
