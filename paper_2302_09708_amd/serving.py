@@ -1,14 +1,16 @@
 """Continuous-batching request loop for CheFSI solves on one GPU.
 
 Requests (a Hamiltonian, a block width Ns, a degree and an iteration count)
-arrive over time.  On arrival a request's potentials and projectors are
-uploaded (its library handle is created) and its exact device footprint is
-known: the orbital block X, the library workspace for its Ns, and the handle's
-own arrays.  A request is admitted, first come first served, as soon as a slot
-is free and its footprint fits in what the admitted requests leave of the HBM
-budget; every admitted request runs its whole solve on its own HIP stream from
-its own host thread, so solves of different sizes overlap on the device.
-Latency is completion minus arrival.
+arrive over time and queue in arrival order.  When a slot is free, the request at
+the head of the queue is opened: its potentials and projectors are uploaded (its
+library handle is created) and its exact device footprint becomes known (the
+orbital block X, the library workspace for its Ns, and the handle's own arrays).
+It is admitted, first come first served, as soon as its footprint fits in what
+the admitted requests leave of the HBM budget; every admitted request runs its
+whole solve on its own HIP stream from its own host thread, so solves of
+different sizes overlap on the device.  Only the head of the queue holds device
+memory while it waits, so the device holds at most the budget plus the arrays of
+one waiting handle.  Latency is completion minus arrival.
 
 The scheduling (``Scheduler``) is independent of the GPU: it calls an
 ``open(request) -> (state, footprint)`` and a ``run(state) -> output`` supplied
@@ -85,8 +87,9 @@ class AdmissionError(RuntimeError):
 class Scheduler:
     """First-come-first-served admission by free slot and HBM footprint.
 
-    open_fn(request) -> (state, footprint_bytes) runs at arrival on the scheduling
-    thread; run_fn(state, slot) -> output runs on the slot's worker thread;
+    open_fn(request) -> (state, footprint_bytes) runs on the scheduling thread when the
+    request is at the head of the queue and a slot is free (so at most one opened request
+    waits for room); run_fn(state, slot) -> output runs on the slot's worker thread;
     close_fn(state) releases what open_fn acquired.  A request whose footprint
     exceeds the whole budget is refused with AdmissionError.  With fail_fast the first
     exception of a solve stops the loop and is raised; otherwise the request's Result
@@ -111,7 +114,8 @@ class Scheduler:
         used = 0
         results: List[Result] = []
         errors: List[BaseException] = []
-        queue: List[Tuple[Request, Any, int, float]] = []  # (request, state, footprint, arrival wall time)
+        arrived: List[Request] = []  # arrived, not opened yet (arrival order)
+        head: Optional[Tuple[Request, Any, int]] = None  # opened, waiting for room
         workers: List[threading.Thread] = []
         t0 = self.clock()
 
@@ -141,42 +145,52 @@ class Scheduler:
                 cv.notify_all()
 
         nxt = 0
-        while True:
-            now = self.clock() - t0
-            # arrivals: upload the request's Hamiltonian and learn its footprint
-            while nxt < len(order) and order[nxt].arrival <= now:
-                req = order[nxt]
-                state, fp = self.open_fn(req)
-                if fp > self.budget:
-                    if self.close_fn is not None:
-                        self.close_fn(state)
-                    raise AdmissionError(f"request {req.rid} needs {fp} bytes, budget {self.budget}")
-                queue.append((req, state, int(fp), req.arrival))
-                nxt += 1
+        try:
+            while True:
                 now = self.clock() - t0
-            with cv:
-                # admit in arrival order while the head fits
-                while queue and free_slots and used + queue[0][2] <= self.budget:
-                    req, state, fp, t_arr = queue.pop(0)
-                    slot = free_slots.pop(0)
-                    used += fp
-                    self.peak_bytes = max(self.peak_bytes, used)
-                    self.peak_active = max(self.peak_active, self.slots - len(free_slots))
-                    th = threading.Thread(target=worker, args=(req, state, fp, slot, t_arr, self.clock() - t0),
-                                          daemon=True)
-                    workers.append(th)
-                    th.start()
-                if nxt >= len(order) and not queue and len(free_slots) == self.slots:
-                    break
-                if errors:
-                    break
-                wait = None if nxt >= len(order) else max(0.0, order[nxt].arrival - (self.clock() - t0))
-                cv.wait(timeout=wait if wait is not None else 1.0)
-        for th in workers:
-            th.join()
-        for _, state, _, _ in queue:  # never admitted (after an error)
-            if self.close_fn is not None:
-                self.close_fn(state)
+                while nxt < len(order) and order[nxt].arrival <= now:
+                    arrived.append(order[nxt])
+                    nxt += 1
+                with cv:
+                    slot_free = bool(free_slots)
+                if head is None and arrived and slot_free and not errors:
+                    # open the head of the queue (upload its Hamiltonian, learn its footprint)
+                    req = arrived.pop(0)
+                    state, fp = self.open_fn(req)
+                    head = (req, state, int(fp))
+                    if fp > self.budget:
+                        head = None
+                        if self.close_fn is not None:
+                            self.close_fn(state)
+                        raise AdmissionError(f"request {req.rid} needs {fp} bytes, budget {self.budget}")
+                with cv:
+                    if head is not None and free_slots and used + head[2] <= self.budget and not errors:
+                        req, state, fp = head
+                        head = None
+                        slot = free_slots.pop(0)
+                        used += fp
+                        self.peak_bytes = max(self.peak_bytes, used)
+                        self.peak_active = max(self.peak_active, self.slots - len(free_slots))
+                        th = threading.Thread(target=worker,
+                                              args=(req, state, fp, slot, req.arrival, self.clock() - t0),
+                                              daemon=True)
+                        workers.append(th)
+                        th.start()
+                        continue
+                    if errors:
+                        break
+                    if nxt >= len(order) and not arrived and head is None and len(free_slots) == self.slots:
+                        break
+                    if head is None and arrived and free_slots:
+                        continue
+                    # wait for a finished solve (room, a slot) or the next arrival
+                    wait = None if nxt >= len(order) else max(0.0, order[nxt].arrival - (self.clock() - t0))
+                    cv.wait(timeout=wait if wait is not None else 1.0)
+        finally:
+            for th in workers:
+                th.join()
+            if head is not None and self.close_fn is not None:  # opened, never admitted
+                self.close_fn(head[1])
         if errors:
             raise errors[0]
         return sorted(results, key=lambda r: r.rid)

@@ -144,3 +144,39 @@ def test_bad_configuration():
         Scheduler(budget_bytes=0, slots=1, open_fn=f.open, run_fn=f.run)
     with pytest.raises(ValueError):
         Scheduler(budget_bytes=10, slots=0, open_fn=f.open, run_fn=f.run)
+
+
+def test_only_the_head_of_the_queue_is_opened():
+    """Handles are created when a request reaches the head of the queue with a slot free:
+    while the first request runs, the second waits opened (it does not fit beside it) and
+    the third is not opened yet."""
+    f = Fake()
+    opened = []
+
+    def open_log(req):
+        opened.append((req.rid, time.perf_counter()))
+        return f.open(req)
+
+    reqs = [_req(0, 0.0, 6, 0.15), _req(1, 0.0, 6, 0.05), _req(2, 0.0, 3, 0.05)]
+    s = Scheduler(budget_bytes=10, slots=4, open_fn=open_log, run_fn=f.run, close_fn=f.close)
+    s.run(reqs)
+    t_open = dict(opened)
+    end = {rid: t for ev, rid, t in f.events if ev == "end"}
+    assert [rid for rid, _ in opened] == [0, 1, 2]
+    assert t_open[2] >= end[0] - 1e-3
+
+
+def test_open_failure_joins_running_solves_and_closes():
+    """An exception from open_fn ends the loop only after the admitted solves finish and
+    are closed."""
+    f = Fake()
+
+    def bad_open(req):
+        if req.rid == 1:
+            raise RuntimeError("upload failed")
+        return f.open(req)
+
+    s = Scheduler(budget_bytes=100, slots=2, open_fn=bad_open, run_fn=f.run, close_fn=f.close)
+    with pytest.raises(RuntimeError, match="upload failed"):
+        s.run([_req(0, 0.0, 1, 0.1), _req(1, 0.01, 1, 0.01)])
+    assert f.closed == [0] and f.active == 0
