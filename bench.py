@@ -288,8 +288,10 @@ def forces_figures(cs, prob, cfg, precision: str):
 
 def kpoint_figures(cs, prob, cfg):
     """The workload's grid, atoms and Ns at the Bloch wavevector k_d = pi / (2 L_d) in
-    complex FP64 (outside the timed steps): step rate and the rate of one H_k application
-    (projector gather + Bloch-phased stencil + scatter, HIP events on the launch stream)."""
+    complex FP64 (outside the timed steps): step rate, per-kernel milliseconds per step
+    (HIP events the library records on the launch stream), the stencil pass's own rate, and
+    the rate of one whole H_k application (coefficient gather, Bloch-phased stencil,
+    projector scatter) counted on the stencil's bytes."""
     import torch
     from paper_2302_09708_amd import inputs
     ns, m = cfg.ns, cfg.degree
@@ -317,6 +319,8 @@ def kpoint_figures(cs, prob, cfg):
     d = h.step(X, ns, m, lo, cut, hi, ws)  # warm-up step
     lo, cut = d[0], d[-1]
     steps = 2
+    h.profile_reset()
+    h.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -324,7 +328,17 @@ def kpoint_figures(cs, prob, cfg):
         lo, cut = d[0], d[-1]
     torch.cuda.synchronize()
     step_ms = (time.perf_counter() - t0) * 1e3 / steps
+    names = ("zhx", "band", "gram", "dense_eig", "rotate")
+    per_kernel = {}
+    for i, name in enumerate(names):
+        ms, n = h.profile_read(i)
+        per_kernel[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps}
     h.close()
+    # the stencil pass's own rate: (3m+1) complex arrays of Nd x Ns move per step (the first
+    # filter pass and the pass forming H X~ read one and write one, the others read two and
+    # write one) plus Veff per launch, over the summed zhx launch time
+    zhx_bytes = 16.0 * prob.nd * ns * (3 * m + 1) + 8.0 * prob.nd * (m + 1)
+    zhx_gbs = zhx_bytes / (per_kernel["zhx"]["ms_per_step"] * 1e-3) / 1e9
     del X, ws
     torch.cuda.empty_cache()
     # algorithmic bytes of one application: read X, write Y (16 B each per point and
@@ -332,6 +346,7 @@ def kpoint_figures(cs, prob, cfg):
     apply_bytes = prob.nd * ns * 32.0 + prob.nd * 8.0
     gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
     return {"k_bohr_inv": list(k), "dtype": "c128", "iter_per_s": 1e3 / step_ms, "ms_per_step": step_ms,
+            "kernels": per_kernel, "zhx_gbs": zhx_gbs, "zhx_frac": zhx_gbs / HBM_PEAK_GBS,
             "apply_h_ms": apply_ms, "apply_h_gbs": gbs, "apply_h_frac": gbs / HBM_PEAK_GBS,
             "ritz_lowest": float(d[0])}
 

@@ -407,6 +407,18 @@ int chefsi_kpoint_apply_h(chefsi_kpoint_t* h, const void* X, void* Y, int32_t ns
 int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, double lam_lo, double lam_cut,
                        double lam_hi, void* ws, size_t ws_bytes, void* stream, double* ritz_host);
 
+/* Per-kernel timing of a k-point handle, as chefsi_profile_* for the real handle (HIP
+ * events on the call's stream, off by default, no effect on results).  kernel ids:
+ * 0 zhx (Bloch-phased stencil pass), 1 band passes (projector scatter and coefficient
+ * gather, with their reductions), 2 projection (zgemm batches and the partial sums),
+ * 3 dense stage (zpotrf, ztrsm, zheevd), 4 rotation (zgemm row panels and the copy
+ * back).  chefsi_kpoint_profile_read synchronizes on the recorded events and returns
+ * the summed milliseconds and launch count since the last reset; ids outside 0..4 are
+ * CHEFSI_ERR_INVALID_ARG. */
+int chefsi_kpoint_profile_enable(chefsi_kpoint_t* h, int32_t on);
+int chefsi_kpoint_profile_reset(chefsi_kpoint_t* h);
+int chefsi_kpoint_profile_read(chefsi_kpoint_t* h, int32_t kernel_id, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

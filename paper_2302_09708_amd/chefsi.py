@@ -45,6 +45,7 @@ EXPORTS = (
     "chefsi_update_veff", "chefsi_forces_workspace_bytes", "chefsi_nonlocal_forces",
     "chefsi_kinetic_stress", "chefsi_kpoint_create", "chefsi_kpoint_destroy", "chefsi_kpoint_last_error",
     "chefsi_kpoint_workspace_bytes", "chefsi_kpoint_apply_h", "chefsi_kpoint_step",
+    "chefsi_kpoint_profile_enable", "chefsi_kpoint_profile_reset", "chefsi_kpoint_profile_read",
     "chefsi_set_stencil_tiling", "chefsi_get_stencil_tiling", "chefsi_nonlocal_stress",
     "chefsi_static_scratch_bytes", "chefsi_apply_h_static", "chefsi_set_projector_pass",
     "chefsi_autotune",
@@ -131,6 +132,9 @@ def load(path: str = LIB_PATH):
     lib.chefsi_kpoint_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     lib.chefsi_kpoint_apply_h.argtypes = [vp, vp, vp, i32, vp, sz, vp]
     lib.chefsi_kpoint_step.argtypes = [vp, vp, i32, i32, dbl, dbl, dbl, vp, sz, vp, pd]
+    lib.chefsi_kpoint_profile_enable.argtypes = [vp, i32]
+    lib.chefsi_kpoint_profile_reset.argtypes = [vp]
+    lib.chefsi_kpoint_profile_read.argtypes = [vp, i32, pd, C.POINTER(C.c_int64)]
     _lib = lib
     return lib
 
@@ -238,6 +242,17 @@ class KPoint:
                                                   ws.numel() * ws.element_size(), _stream(stream),
                                                   d.ctypes.data_as(C.POINTER(C.c_double))))
         return d
+
+    def profile_enable(self, on: bool = True):
+        self._check(self._lib.chefsi_kpoint_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        self._check(self._lib.chefsi_kpoint_profile_reset(self.h))
+
+    def profile_read(self, kernel_id: int) -> Tuple[float, int]:
+        ms, n = C.c_double(0.0), C.c_int64(0)
+        self._check(self._lib.chefsi_kpoint_profile_read(self.h, int(kernel_id), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
 
 class Handle:

@@ -408,12 +408,15 @@ T* at(void* ws, size_t off) {
 }
 
 // ---- profiling -------------------------------------------------------------
-struct ProfScope {
-  chefsi_handle* h;
+// HIP events around the launches of one kernel class on the call's stream (any handle type
+// with prof_on, ev_pool, ev_pending, prof_ms and prof_n).
+template <typename H>
+struct ProfScopeT {
+  H* h;
   hipStream_t s;
   int id;
   hipEvent_t b = nullptr, e = nullptr;
-  ProfScope(chefsi_handle* h_, int id_, hipStream_t s_) : h(h_), s(s_), id(id_) {
+  ProfScopeT(H* h_, int id_, hipStream_t s_) : h(h_), s(s_), id(id_) {
     if (!h->prof_on) return;
     b = take();
     e = take();
@@ -435,13 +438,15 @@ struct ProfScope {
     h->ev_pending.push_back({id, b, e});
     b = e = nullptr;
   }
-  ~ProfScope() {
+  ~ProfScopeT() {
     if (b) h->ev_pool.push_back(b);
     if (e) h->ev_pool.push_back(e);
   }
 };
+using ProfScope = ProfScopeT<chefsi_handle>;
 
-void prof_collect(chefsi_handle* h) {
+template <typename H>
+void prof_collect(H* h) {
   for (auto& p : h->ev_pending) {
     HIP_TRY(hipEventSynchronize(p.e));
     float ms = 0.f;
@@ -2470,6 +2475,11 @@ struct chefsi_kpoint {
   double* pinned = nullptr;
   rocblas_handle blas = nullptr;
   std::map<int, size_t> solver_ws_cache;
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<EventPair> ev_pending;
+  double prof_ms[kNumProf] = {0};
+  int64_t prof_n[kNumProf] = {0};
   std::string last_error;
 };
 
@@ -2510,15 +2520,19 @@ size_t zsolver_workspace(chefsi_kpoint* h, int ns) {
     rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_upper, ns, nullptr, ns, nullptr, nullptr, nullptr);
   });
   const BlasGram kg = plan_blas_gram(h->nd, ns);
-  query([&] {
-    rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns,
-                                  (rocblas_int)kg.kc, &one, nullptr, ld, kg.kc, nullptr, ld, kg.kc, &one, nullptr, ns,
-                                  (rocblas_stride)ns * ns, kg.splits);
-  });
-  query([&] {
-    rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns, ld, &one, nullptr,
-                  ld, nullptr, ld, &one, nullptr, ns);
-  });
+  for (int q = 0; q < kg.nblk; ++q) {
+    const int m = kg.start[q + 1] - kg.start[q], n = ns - kg.start[q];
+    query([&] {
+      rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n,
+                                    (rocblas_int)kg.kc, &one, nullptr, ld, kg.kc, nullptr, ld, kg.kc, &one, nullptr,
+                                    ns, (rocblas_stride)ns * ns, kg.splits);
+    });
+    if (kg.tail > 0)
+      query([&] {
+        rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n,
+                      (rocblas_int)kg.tail, &one, nullptr, ld, nullptr, ld, &one, nullptr, ns);
+      });
+  }
   const rocblas_int prow = (rocblas_int)std::max<int64_t>(1, std::min<int64_t>(h->nd, (((int64_t)1 << 31) - 1) / ns));
   query([&] {
     rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, prow, ns, ns, &one, nullptr, ld, nullptr,
@@ -2579,9 +2593,18 @@ void krelease(chefsi_kpoint* h) {
                   h->partial};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto& p : h->ev_pending) {
+    (void)hipEventDestroy(p.b);
+    (void)hipEventDestroy(p.e);
+  }
+  for (auto ev : h->ev_pool) (void)hipEventDestroy(ev);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->blas) rocblas_destroy_handle(h->blas);
 }
+
+// k-point kernel classes timed by chefsi_kpoint_profile_*
+enum KProfId { KP_ZHX = 0, KP_BAND = 1, KP_GRAM = 2, KP_EIG = 3, KP_ROT = 4 };
+using KProfScope = ProfScopeT<chefsi_kpoint>;
 
 ZNbArgs zband_args(const chefsi_kpoint* h, double2* y, int ns, const double2* alpha, double sa) {
   ZNbArgs b{};
@@ -2611,8 +2634,10 @@ ZNbArgs zband_args(const chefsi_kpoint* h, double2* y, int ns, const double2* al
 void zapply(chefsi_kpoint* h, const double2* x, const double2* prev, double2* out, int ns, double sa, double sc,
             double sb, double2* alpha, hipStream_t s, bool alpha_ready = false, bool want_next = false) {
   if (h->np_tot > 0 && !alpha_ready) {
+    KProfScope ps(h, KP_BAND, s);
     HIP_TRY(launch_zband(zband_args(h, const_cast<double2*>(x), ns, alpha, 0.0), false, true, s));
     HIP_TRY(launch_zband_reduce(h->partial, h->q_slot_ptr, h->q_slot, h->gdv, h->np_tot, ns, alpha, s));
+    ps.done();
   }
   ZHxArgs a{};
   a.x = x;
@@ -2634,11 +2659,17 @@ void zapply(chefsi_kpoint* h, const double2* x, const double2* prev, double2* ou
   a.sa = sa;
   a.sc = sc;
   a.sb = sb;
-  HIP_TRY(launch_zhx(a, ns, s));
+  {
+    KProfScope ps(h, KP_ZHX, s);
+    HIP_TRY(launch_zhx(a, ns, s));
+    ps.done();
+  }
   if (h->np_tot > 0) {
+    KProfScope ps(h, KP_BAND, s);
     HIP_TRY(launch_zband(zband_args(h, out, ns, alpha, sa), true, want_next, s));
     if (want_next)
       HIP_TRY(launch_zband_reduce(h->partial, h->q_slot_ptr, h->q_slot, h->gdv, h->np_tot, ns, alpha, s));
+    ps.done();
   }
 }
 
@@ -2859,6 +2890,29 @@ void chefsi_kpoint_destroy(chefsi_kpoint_t* h) {
 
 const char* chefsi_kpoint_last_error(const chefsi_kpoint_t* h) { return h ? h->last_error.c_str() : ""; }
 
+int chefsi_kpoint_profile_enable(chefsi_kpoint_t* h, int32_t on) {
+  return kguarded(h, [&] { h->prof_on = on != 0; });
+}
+
+int chefsi_kpoint_profile_reset(chefsi_kpoint_t* h) {
+  return kguarded(h, [&] {
+    prof_collect(h);
+    for (int i = 0; i < kNumProf; ++i) {
+      h->prof_ms[i] = 0.0;
+      h->prof_n[i] = 0;
+    }
+  });
+}
+
+int chefsi_kpoint_profile_read(chefsi_kpoint_t* h, int32_t kernel_id, double* total_ms, int64_t* launches) {
+  return kguarded(h, [&] {
+    check(kernel_id >= 0 && kernel_id <= KP_ROT, "kernel_id out of range");
+    prof_collect(h);
+    if (total_ms) *total_ms = h->prof_ms[kernel_id];
+    if (launches) *launches = h->prof_n[kernel_id];
+  });
+}
+
 int chefsi_kpoint_workspace_bytes(chefsi_kpoint_t* h, int32_t ns, size_t* bytes) {
   return kguarded(h, [&] {
     check(bytes != nullptr, "null pointer");
@@ -2924,21 +2978,35 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
     // split-K: K chunks as one strided batch of products, partials summed in a fixed order
     double2* part = zat<double2>(ws, L.partial);
     const BlasGram& kg = L.kg;
+    // upper triangle only, by the real path's column blocks: block row q of every partial
+    // against columns [start_q, ns)
     auto gram = [&](const double2* A, const double2* Bm, double2* C) {
-      BLAS_TRY(rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none,
-                                             ns, ns, (rocblas_int)kg.kc, &one, zc(A), ld, kg.kc, zc(Bm), ld, kg.kc,
-                                             &zero, zm(part), ns, (rocblas_stride)ns * ns, kg.splits));
-      if (kg.tail > 0) {
-        const int64_t k0 = kg.kc * kg.splits;
-        BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, ns, ns,
-                               (rocblas_int)kg.tail, &one, zc(A + k0), ld, zc(Bm + k0), ld, &zero,
-                               zm(part + (size_t)kg.splits * ns * ns), ns));
+      for (int q = 0; q < kg.nblk; ++q) {
+        const int r0 = kg.start[q], m = kg.start[q + 1] - r0, n = ns - r0;
+        const double2* Aq = A + (size_t)r0 * h->nd;
+        const double2* Bq = Bm + (size_t)r0 * h->nd;
+        double2* Pq = part + r0 + (size_t)r0 * ns;
+        BLAS_TRY(rocblas_zgemm_strided_batched(h->blas, rocblas_operation_conjugate_transpose,
+                                               rocblas_operation_none, m, n, (rocblas_int)kg.kc, &one, zc(Aq), ld,
+                                               kg.kc, zc(Bq), ld, kg.kc, &zero, zm(Pq), ns, (rocblas_stride)ns * ns,
+                                               kg.splits));
+        if (kg.tail > 0) {
+          const int64_t k0 = kg.kc * kg.splits;
+          BLAS_TRY(rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n,
+                                 (rocblas_int)kg.tail, &one, zc(Aq + k0), ld, zc(Bq + k0), ld, &zero,
+                                 zm(Pq + (size_t)kg.splits * ns * ns), ns));
+        }
       }
       HIP_TRY(launch_zsum_partials(part, kg.nparts, ns, C, s));
     };
-    gram(Xf, Yf, Hs);
-    gram(Xf, Xf, Ms);
+    {
+      KProfScope ps(h, KP_GRAM, s);
+      gram(Xf, Yf, Hs);
+      gram(Xf, Xf, Ms);
+      ps.done();
+    }
     // Hermitian-definite eigenproblem (Alg. 1, Diagonalization)
+    KProfScope pe(h, KP_EIG, s);
     BLAS_TRY(rocsolver_zpotrf(h->blas, rocblas_fill_upper, ns, zm(Ms), ns, info));
     BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
                            rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
@@ -2948,6 +3016,8 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
                               zat<double>(ws, L.e), info + 1));
     BLAS_TRY(rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
                            rocblas_diagonal_non_unit, ns, ns, &one, zc(Ms), ns, zm(Hs), ns));
+    pe.done();
+    KProfScope pr(h, KP_ROT, s);
     // rotation (Alg. 1, Rotation): X = X~ Z into the buffer Y~ held, in row panels of fewer
     // than 2^31 output elements each (blocks of any size)
     const int64_t prow = std::max<int64_t>(1, std::min<int64_t>(h->nd, (((int64_t)1 << 31) - 1) / ns));
@@ -2957,6 +3027,7 @@ int chefsi_kpoint_step(chefsi_kpoint_t* h, void* X, int32_t ns, int32_t degree, 
                              ld, zc(Hs), ns, &zero, zm(Yf + r0), ld));
     }
     if (Yf != A) HIP_TRY(hipMemcpyAsync(A, Yf, (size_t)h->nd * ns * 16, hipMemcpyDeviceToDevice, s));
+    pr.done();
     double* d = h->pinned;
     rocblas_int* inf = reinterpret_cast<rocblas_int*>(h->pinned + h->max_ns);
     HIP_TRY(hipMemcpyAsync(d, D, (size_t)ns * 8, hipMemcpyDeviceToHost, s));

@@ -233,3 +233,28 @@ def test_block_above_2_31_elements(cs):
     assert orth < 1e-10
     assert ritz < 1e-10
     h.close()
+
+
+def test_profile_counts_launches(cs):
+    """Per-kernel timing of a k-point handle: one step of degree m records m + 1 stencil
+    passes, m + 2 band passes (the gather-only pass on X, one per application), one
+    projection, one dense stage and one rotation; an unknown id is refused."""
+    prob = inputs.small_problem(**CASES[0][1])
+    img = inputs.support_images(prob)
+    ns, degree = 8, 6
+    h = cs.KPoint(prob, CASES[0][2], img, max_ns=ns)
+    ws = h.workspace(ns)
+    X = _dev(_block(prob.nd, ns, 9))
+    h.profile_enable(True)
+    h.profile_reset()
+    h.step(X, ns, degree, -3.0, 2.0, 200.0, ws)
+    counts = [h.profile_read(i)[1] for i in range(5)]
+    times = [h.profile_read(i)[0] for i in range(5)]
+    print(f"launch counts {counts}, ms {[round(t, 3) for t in times]}", flush=True)
+    assert counts == [degree + 1, degree + 2, 1, 1, 1]
+    assert all(t > 0.0 for t in times)
+    with pytest.raises(cs.ChefsiError):
+        h.profile_read(5)
+    h.profile_reset()
+    assert h.profile_read(0) == (0.0, 0)
+    h.close()
