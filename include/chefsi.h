@@ -153,10 +153,13 @@ int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32
  * take it inside the stencil pass from per-point records, the others in a separate
  * scatter pass, after a gather of the coefficients over each atom's support.
  * in_stencil = 0 (band pass): the stencil pass runs without records, and one pass over
- * the touched points, region by region (a z plane x a band of rows), adds every
- * projector term and forms, from the finished values, fixed-order partial sums of the
- * next application's coefficients (the filter carries them from one application to the
- * next).  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
+ * the touched points, region by region (runs of consecutive touched points, each with at
+ * most 512 points, 128 projectors and 1920 projector entries), adds every projector term
+ * and forms, from the finished values, fixed-order partial sums of the next
+ * application's coefficients (the filter carries them from one application to the
+ * next).  A grid point inside more than 128 projector supports fits no region: the band
+ * pass is then refused with CHEFSI_ERR_INVALID_ARG and the handle stays on the record
+ * route.  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
  * orbitals on the device); for tuning and tests, not while calls on the handle are in
  * flight. */
 int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
@@ -167,7 +170,8 @@ int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
  * filter-form H applications per candidate on the first min(ns, 1024) orbitals of the
  * device block X (read only; the workspace block takes the results), on `stream`, which
  * the call synchronises.  Keeps the fastest and, when choice is not NULL, writes
- * {rows per thread, row groups, in_stencil} to choice[0..2].  Results after tuning agree
+ * {rows per thread, row groups, in_stencil} to choice[0..2] (the band pass is skipped
+ * when chefsi_set_projector_pass would refuse it).  Results after tuning agree
  * with the untuned ones to rounding (the same terms summed in another order).  ws as for
  * chefsi_apply_h with this ns.  A one-time set-up call, like a library benchmark mode. */
 int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
@@ -379,6 +383,9 @@ int chefsi_version(void);
  * (re, im), Nd x ns column major (ld = Nd): a torch.complex128 tensor of shape
  * (ns, Nd).  A step is Alg. 1 with conjugate transposes: Hs = X~^H H X~,
  * Ms = X~^H X~, Hs Z = Ms Z D (Hermitian definite, ascending D), X = X~ Z.
+ * The projector term is added by a band pass like the real handle's (see
+ * chefsi_set_projector_pass), so a grid point may lie in at most 128 projector supports
+ * (CHEFSI_ERR_INVALID_ARG at create otherwise).
  * The handle holds its own copies of all host inputs (freed by
  * chefsi_kpoint_destroy); calls are ordered on their stream; Nd < 2^31 and
  * max_ns <= min(Nd, 65535) (CHEFSI_ERR_INVALID_ARG otherwise); a block may hold

@@ -2301,6 +2301,24 @@ static float time_filter_launch(chefsi_handle* h, const T* X, T* B, int ns, T* a
 }
 }  // extern "C++"
 
+// Switch the projector route of a handle with projectors (mode 4: records in the stencil
+// pass, 0: band pass).  The band tables are built before anything else changes, so a
+// route that cannot be built (a point in more than kBandMaxSlots projector supports)
+// throws and leaves the handle on its current route.
+static void set_projector_route(chefsi_handle* h, int mode) {
+  if (mode == 0) {
+    build_band_tables(h);
+    h->rec_max = 0;
+    build_hx_records(h, h->hx_plan);
+    build_scatter_records(h);
+  } else {
+    h->rec_max = mode;
+    build_hx_records(h, h->hx_plan);
+    build_scatter_records(h);
+    free_band_tables(h);
+  }
+}
+
 int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, size_t ws_bytes, void* stream,
                     int32_t* choice) {
   return guarded(h, [&] {
@@ -2340,12 +2358,12 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
     for (int mode : modes) {
       if (h->np_tot == 0 && mode == 0) continue;
       if (h->rec_max != mode) {
-        h->rec_max = mode;
-        build_scatter_records(h);
-        if (mode == 0)
-          build_band_tables(h);
-        else
-          free_band_tables(h);
+        try {
+          set_projector_route(h, mode);
+        } catch (const Error& e) {
+          if (mode == 0 && e.status == CHEFSI_ERR_INVALID_ARG) continue;  // no band route for this handle
+          throw;
+        }
       }
       for (size_t c = 0; c < cands.size(); ++c) {
         if (h->np_tot > 0)
@@ -2367,14 +2385,7 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
       }
     }
     h->prof_on = prof;
-    if (h->rec_max != best_mode) {
-      h->rec_max = best_mode;
-      build_scatter_records(h);
-      if (best_mode == 0)
-        build_band_tables(h);
-      else
-        free_band_tables(h);
-    }
+    if (h->rec_max != best_mode) set_projector_route(h, best_mode);
     if (h->np_tot > 0)
       build_hx_records(h, cands[best_c]);
     else
@@ -2395,13 +2406,7 @@ int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil) {
       h->rec_max = want;
       return;
     }
-    h->rec_max = want;
-    build_hx_records(h, h->hx_plan);
-    build_scatter_records(h);
-    if (want == 0)
-      build_band_tables(h);
-    else
-      free_band_tables(h);
+    set_projector_route(h, want);
   });
 }
 

@@ -199,3 +199,38 @@ def test_band_pass_step_and_solve(cs):
     k = oc.gap_index(d_ref, int(ns / 1.2))
     assert np.abs(d[:k] - d_ref[:k]).max() <= 1e-5
     assert oc.subspace_residual(x_ref, host(Xm), k) <= 1e-5
+
+
+def test_point_in_too_many_supports_keeps_the_record_route(cs):
+    """40 atoms x 4 projectors around one point (160 projector entries there, above the 128
+    projectors a band region holds): asking for the band pass is refused and leaves the
+    handle on the record route (H X still the oracle's), and autotune keeps the records."""
+    n, hh, bc = (16, 16, 16), (0.3, 0.3, 0.3), (0, 0, 0)
+    center = np.array([8.0, 8.0, 8.0]) * 0.3
+    rng = np.random.Generator(np.random.PCG64(77))
+    atoms = center + rng.uniform(-0.25, 0.25, size=(40, 3))
+    sp, si, npj, chi, gam = inputs.kb_projectors(n, hh, bc, atoms, 4)
+    veff = inputs.gaussian_wells(n, hh, bc, atoms)
+    prob = inputs.Problem(n, hh, bc, 12, veff, atoms, sp, si, npj, chi, gam, name="crowded")
+    cnt = np.bincount(si, weights=np.repeat(npj, np.diff(sp)), minlength=prob.nd)
+    assert cnt.max() > 128
+    ns = 6
+    x = inputs.initial_block(prob.nd, ns, 3).T
+    ref = apply_h(prob, x)
+    h = cs.Handle(prob, precision=cs.FP64, max_ns=ns)
+    ws = cs.workspace(h, ns)
+
+    def check():
+        Y = torch.zeros((ns, prob.nd), dtype=torch.float64, device="cuda")
+        h.chefsi_apply_h(dev(x), Y, ns, ws)
+        err = np.abs(host(Y) - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, err
+
+    with pytest.raises(cs.ChefsiError, match="too many projector supports"):
+        h.chefsi_set_projector_pass(False)
+    check()
+    py, nyg, in_stencil = h.chefsi_autotune(dev(x), ns, ws)
+    print(f"autotune on the crowded grid: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
+    assert in_stencil
+    check()
+    h.close()
