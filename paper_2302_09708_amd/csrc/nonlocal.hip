@@ -146,10 +146,12 @@ hipError_t launch_nl_scatter(const NsArgs<TC, TO>& a, hipStream_t s) {
 }
 
 // Orbitals per group: a group's final values of the region's points sit in LDS
-// (kBandMaxPts * G * sizeof(TC) = 32 KB) beside the staged coefficients and the entry
-// tables, 80 KB in all, so two blocks share a CU.
+// (kBandMaxPts * G * sizeof(TC): 32 KB in FP64, 16 KB in FP32) beside the staged
+// coefficients and the entry tables (80 KB in all in FP64: two blocks share a CU).  Eight
+// orbitals per group in FP32 too: measured against 16 and 4 (120^3, Ns 7200: 592 vs 609
+// and 709 ms per step; 72^3 mixed: 7.5 vs 7.9 and 8.3 ms).
 template <typename TC>
-constexpr int band_g() { return sizeof(TC) == 8 ? 8 : 16; }
+constexpr int band_g() { return 8; }
 
 // One block per (region, run of orbital groups), one thread per point.  The region's
 // entry tables go to LDS once; then, group by group, the point values and the staged
