@@ -26,16 +26,21 @@ def cs():
     return chefsi
 
 
+@pytest.mark.parametrize("route", ["records", "band"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_static_apply_h_equals_workspace_apply_h(cs, prec):
+def test_static_apply_h_equals_workspace_apply_h(cs, prec, route):
+    """Both projector routes: the record route (coefficients gathered first, added inside the
+    stencil pass and by the scatter pass) and the band pass (coefficients gathered by a
+    band pass; its partial sums live in the handle's own arrays)."""
     prob = inputs.small_problem(n=(26, 21, 19), h=(0.3, 0.28, 0.32), bc=(0, 1, 0), fd_order=12, n_atoms=7,
                                 nproj_per_atom=4, seed=41)
     dt = "float64" if prec == "fp64" else "float32"
     h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=9)
+    h.chefsi_set_projector_pass(route == "records")
     ws = cs.workspace(h, 9)
     rng = np.random.default_rng(17)
     for ns in (9, 4):  # second call smaller than the first
-        print(f"static apply_h: {prec} ns={ns}", flush=True)
+        print(f"static apply_h: {prec} {route} ns={ns}", flush=True)
         x = rng.standard_normal((prob.nd, ns)).astype(dt)
         X = dev(x, dt)
         Y_ws = torch.empty_like(X)
