@@ -101,6 +101,11 @@ CONFIGS: Dict[str, Config] = {
     # small enough for the FP64 oracle to run whole iterations on the host.
     "cfg3_twin": Config("cfg3_twin", (30, 30, 90), (0.3, 0.3, 0.3), (0, 0, 1), "slab", 25, 4,
                         300, 24, 6, 1013, 2013, lattice_cells=(3, 3, 3)),
+    # Reduced twin of cfg4 (half the cell per direction at the same spacing and atom density:
+    # 125 atoms from a jittered FCC 4^3 lattice, Ns 900, degree 16): whole oracle iterations
+    # fit on the host.
+    "cfg4_twin": Config("cfg4_twin", (60, 60, 60), (0.22, 0.22, 0.22), (0, 0, 0), "fcc_subset", 125, 4,
+                        900, 16, 6, 1014, 2014, lattice_cells=(4, 4, 4)),
     # Test-sized slab (same recipe), for mixed/FP64 parity of whole iterations.
     "slab_small": Config("slab_small", (16, 16, 48), (0.3, 0.3, 0.3), (0, 0, 1), "slab", 6, 4,
                          48, 24, 6, 1023, 2023, lattice_cells=(2, 2, 2)),

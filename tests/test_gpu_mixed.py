@@ -237,9 +237,9 @@ def test_mixed_falls_back_to_fp64_on_ill_conditioned_blocks(cs, k):
     assert err <= 1e-5
 
 
-def _golden_twin():
+def _golden_twin(name="cfg3_twin_ritz.txt"):
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_twin_ritz.txt")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     rows, bounds = [], None
     for line in open(path):
         if line.startswith("# bounds of the first step"):
@@ -281,6 +281,50 @@ def test_cfg3_twin_solves_against_stored_oracle_ritz_values(cs):
     res = oc.residual_norms(prob, xmx[:, :k], dmx[:k])
     res64 = oc.residual_norms(prob, x64[:, :k], d64[:k])
     print(f"cfg3 twin: N_chk={k} FP64 max|dRitz|={err64:.2e} mixed max|dRitz|={errmx:.2e} rho(mixed, FP64)={rho:.2e} "
+          f"max residual mixed {res.max():.2e} FP64 {res64.max():.2e}", flush=True)
+    assert err64 <= 1e-10
+    assert errmx <= 1e-5
+    assert rho <= 1e-5
+    assert np.abs(xmx.T @ xmx - np.eye(cfg.ns)).max() <= 1e-5
+    assert res.max() <= res64.max() + 1e-4 * max(abs(lo), abs(hi))
+
+
+def test_cfg4_twin_solves_against_stored_oracle_ritz_values(cs):
+    """The reduced cfg4 workload (60^3 periodic at h = 0.22, 125 atoms x 4 projectors from a
+    jittered FCC 4^3 lattice: cfg4's spacing and atom density; Ns 900, degree 16, 6 filter
+    passes): FP64 solve against the oracle's Ritz values (stored by
+    tests/golden/make_cfg4_twin_ritz.py, oracle only, ~80 minutes on the host) to 1e-10 Ha;
+    mixed solve (5 mixed steps + FP64 refinement) to 1e-5 Ha on the gap-bounded leading
+    block, its subspace against the FP64 solve's (rho <= 1e-5), and the residuals of every
+    tenth leading mixed vector under the oracle's H against the FP64 solve's."""
+    cfg = inputs.CONFIGS["cfg4_twin"]
+    prob = inputs.make_problem(cfg)
+    bounds, rows = _golden_twin("cfg4_twin_ritz.txt")
+    assert len(rows) == cfg.n_iter
+    d_ref = rows[cfg.n_iter - 1]
+    lo, cut, hi = oc.spectral_bounds(prob)
+    assert np.allclose((lo, cut, hi), bounds, rtol=1e-14, atol=0)
+    x0 = inputs.initial_block(prob.nd, cfg.ns, cfg.x_seed)
+    k = oc.gap_index(d_ref, int(cfg.ns / 1.2))
+    out = {}
+    for prec, dt in ((cs.FP64, "float64"), (cs.MIXED, "float32")):
+        print(f"cfg4 twin solve precision {prec}", flush=True)
+        h, ws = _handle(cs, prob, cfg.ns, prec)
+        Xd = torch.from_numpy(x0).to(device="cuda", dtype=getattr(torch, dt))
+        d, _, _ = h.solve(Xd, cfg.ns, cfg.degree, cfg.n_iter, ws, bounds=(lo, cut, hi))
+        out[prec] = (d, host(Xd))
+        h.close()
+        del Xd, ws
+        torch.cuda.empty_cache()
+    d64, x64 = out[cs.FP64]
+    dmx, xmx = out[cs.MIXED]
+    err64 = np.abs(d64 - d_ref).max()
+    errmx = np.abs(dmx[:k] - d_ref[:k]).max()
+    rho = oc.subspace_residual(x64, xmx, k)
+    cols = np.arange(0, k, 10)
+    res = oc.residual_norms(prob, xmx[:, cols], dmx[cols])
+    res64 = oc.residual_norms(prob, x64[:, cols], d64[cols])
+    print(f"cfg4 twin: N_chk={k} FP64 max|dRitz|={err64:.2e} mixed max|dRitz|={errmx:.2e} rho(mixed, FP64)={rho:.2e} "
           f"max residual mixed {res.max():.2e} FP64 {res64.max():.2e}", flush=True)
     assert err64 <= 1e-10
     assert errmx <= 1e-5
