@@ -331,3 +331,47 @@ def test_cfg4_twin_solves_against_stored_oracle_ritz_values(cs):
     assert rho <= 1e-5
     assert np.abs(xmx.T @ xmx - np.eye(cfg.ns)).max() <= 1e-5
     assert res.max() <= res64.max() + 1e-4 * max(abs(lo), abs(hi))
+
+
+def test_cfg2_ten_iterations_against_stored_oracle_ritz_values(cs):
+    """The headline workload itself (72^3 periodic at h = 0.25, 128 atoms x 4 projectors,
+    Ns 600, degree 20, 10 filter passes from the seeded X0): FP64 solve against the oracle's
+    Ritz values after 10 iterations (stored by tests/golden/make_cfg2_ritz.py, oracle only,
+    ~35 minutes on the host) to 1e-10 Ha on all Ns; mixed solve (9 mixed steps + FP64
+    refinement) to 1e-5 Ha on the gap-bounded leading block, its subspace against the FP64
+    solve's (rho <= 1e-5), and the residuals of every twentieth leading vector under the
+    oracle's H."""
+    cfg = inputs.CONFIGS["cfg2"]
+    prob = inputs.make_problem(cfg)
+    bounds, rows = _golden_twin("cfg2_ritz.txt")
+    assert len(rows) == cfg.n_iter
+    d_ref = rows[cfg.n_iter - 1]
+    lo, cut, hi = oc.spectral_bounds(prob)
+    assert np.allclose((lo, cut, hi), bounds, rtol=1e-14, atol=0)
+    x0 = inputs.initial_block(prob.nd, cfg.ns, cfg.x_seed)
+    k = oc.gap_index(d_ref, int(cfg.ns / 1.2))
+    out = {}
+    for prec, dt in ((cs.FP64, "float64"), (cs.MIXED, "float32")):
+        print(f"cfg2 solve precision {prec}", flush=True)
+        h, ws = _handle(cs, prob, cfg.ns, prec)
+        Xd = torch.from_numpy(x0).to(device="cuda", dtype=getattr(torch, dt))
+        d, _, _ = h.solve(Xd, cfg.ns, cfg.degree, cfg.n_iter, ws, bounds=(lo, cut, hi))
+        out[prec] = (d, host(Xd))
+        h.close()
+        del Xd, ws
+        torch.cuda.empty_cache()
+    d64, x64 = out[cs.FP64]
+    dmx, xmx = out[cs.MIXED]
+    err64 = np.abs(d64 - d_ref).max()
+    errmx = np.abs(dmx[:k] - d_ref[:k]).max()
+    rho = oc.subspace_residual(x64, xmx, k)
+    cols = np.arange(0, k, 20)
+    res = oc.residual_norms(prob, xmx[:, cols], dmx[cols])
+    res64 = oc.residual_norms(prob, x64[:, cols], d64[cols])
+    print(f"cfg2: N_chk={k} FP64 max|dRitz|={err64:.2e} mixed max|dRitz|={errmx:.2e} rho(mixed, FP64)={rho:.2e} "
+          f"max residual mixed {res.max():.2e} FP64 {res64.max():.2e}", flush=True)
+    assert err64 <= 1e-10
+    assert errmx <= 1e-5
+    assert rho <= 1e-5
+    assert np.abs(xmx.T @ xmx - np.eye(cfg.ns)).max() <= 1e-5
+    assert res.max() <= res64.max() + 1e-4 * max(abs(lo), abs(hi))
