@@ -143,7 +143,9 @@ int chefsi_handle_bytes(const chefsi_handle_t* h, size_t* bytes);
  * for one row per thread, 512 otherwise).  chefsi_set_stencil_tiling(h, 0, 0) restores the
  * library's choice; another pair replaces it (the projector records are rebuilt) and
  * returns CHEFSI_ERR_INVALID_ARG, keeping the current tiling, when it does not fit the
- * grid (rows_per_thread 1..2).  Results agree across tilings to rounding (each point
+ * grid (rows_per_thread 1..4; the library's own choice uses 1 or 2), or, on the record
+ * route, when the tile is too tall for the block's projector coefficients and partial sums
+ * in LDS.  Results agree across tilings to rounding (each point
  * sums the same terms; the last bits can differ).  For tuning and tests.
  * chefsi_get_stencil_tiling writes {rows_per_thread, row_groups, tile rows, halo values
  * per thread} to tiling[0..3]. */
@@ -159,14 +161,16 @@ int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32
  * application's coefficients (the filter carries them from one application to the
  * next).  A grid point inside more than 128 projector supports fits no region: the band
  * pass is then refused with CHEFSI_ERR_INVALID_ARG and the handle stays on the record
- * route.  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
+ * route; the record route is refused, the handle staying on the band pass, when the
+ * current tiling leaves no LDS for its records.  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
  * orbitals on the device); for tuning and tests, not while calls on the handle are in
  * flight. */
 int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
 
 /* Picks the stencil tiling and the projector split by timing them (the planner's
- * tilings of at least r + 1 rows, each with the projector term in the stencil pass for
- * points inside at most four entries and with every term in the scatter pass): three
+ * tilings of at least r + 1 rows with 1 to 4 rows per thread, each with the projector term
+ * in the stencil pass for points inside at most four entries, where the records fit in LDS,
+ * and with every term in the band pass): three
  * filter-form H applications per candidate on the first min(ns, 1024) orbitals of the
  * device block X (read only; the workspace block takes the results), on `stream`, which
  * the call synchronises.  Keeps the fastest and, when choice is not NULL, writes

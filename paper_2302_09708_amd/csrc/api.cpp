@@ -1071,17 +1071,24 @@ T* upload(chefsi_handle* h, const T* src, size_t n) {
 
 // Stencil-pass projector records for tiling hp (points in one to four projector entries,
 // grouped by (y tile, z plane); at most ty * nx per group <= PY * threads), replacing the
-// handle's current ones.  The LDS budget is checked for the longest z chunk (zc = nz),
-// which the planner picks for wide blocks.
-void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
-  const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
-  const int64_t nd = h->nd;
+// handle's current ones.  The LDS budget (the alpha row and the partial-sum buffers
+// beside the tile) is checked for the longest z chunk (zc = nz), which the planner picks
+// for wide blocks; with no records (band route) the pass carries neither.
+static bool hx_records_fit(const chefsi_handle* h, const HxPlan& hp) {
   HxPlan worst = hp;
-  worst.zc = nz;
+  worst.zc = h->n[2];
+  const int nx = h->n[0];
   const size_t lds_need = std::max(hx_lds_bytes(worst, nx, h->radius, h->precision == CHEFSI_FP64 ? 8 : 4,
                                                 h->np_tot, 8),
                                    hx_lds_bytes(worst, nx, h->radius, 4, h->np_tot, 8));
-  check(lds_need <= kHxMaxLds, "too many projectors for the stencil pass (alpha row does not fit in LDS)");
+  return lds_need <= kHxMaxLds;
+}
+
+void build_hx_records(chefsi_handle* h, const HxPlan& hp) {
+  const int nx = h->n[0], ny = h->n[1], nz = h->n[2];
+  const int64_t nd = h->nd;
+  check(h->rec_max == 0 || hx_records_fit(h, hp),
+        "too many projectors for the stencil pass (alpha row does not fit in LDS)");
   const int64_t nkeys = (int64_t)hp.nty * nz;
   auto key_of = [&](int64_t i) {
     const int y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
@@ -2270,7 +2277,7 @@ int chefsi_lanczos_bound(chefsi_handle_t* h, const void* v0, int32_t steps, void
 
 int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32_t row_groups) {
   return guarded(h, [&] {
-    check(rows_per_thread >= 0 && rows_per_thread <= 2 && row_groups >= 0, "tiling parameters out of range");
+    check(rows_per_thread >= 0 && rows_per_thread <= 4 && row_groups >= 0, "tiling parameters out of range");
     check((rows_per_thread == 0) == (row_groups == 0), "give both tiling parameters, or neither");
     const int eb = h->precision == CHEFSI_FP64 ? 8 : 4;
     const HxPlan p = plan_hx(h->n[0], h->n[1], h->n[2], 1, h->radius, eb, rows_per_thread, row_groups);
@@ -2303,8 +2310,9 @@ static float time_filter_launch(chefsi_handle* h, const T* X, T* B, int ns, T* a
 
 // Switch the projector route of a handle with projectors (mode 4: records in the stencil
 // pass, 0: band pass).  The band tables are built before anything else changes, so a
-// route that cannot be built (a point in more than kBandMaxSlots projector supports)
-// throws and leaves the handle on its current route.
+// route that cannot be built (a point in more than kBandMaxSlots projector supports, or
+// records whose LDS does not fit the current tiling) throws and leaves the handle on its
+// current route.
 static void set_projector_route(chefsi_handle* h, int mode) {
   if (mode == 0) {
     build_band_tables(h);
@@ -2312,6 +2320,7 @@ static void set_projector_route(chefsi_handle* h, int mode) {
     build_hx_records(h, h->hx_plan);
     build_scatter_records(h);
   } else {
+    check(hx_records_fit(h, h->hx_plan), "too many projectors for the stencil pass (alpha row does not fit in LDS)");
     h->rec_max = mode;
     build_hx_records(h, h->hx_plan);
     build_scatter_records(h);
@@ -2333,7 +2342,7 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
     // candidate tilings: every row count per thread and row-group count the planner accepts,
     // tall tiles only (at least r + 1 rows, or the whole y extent)
     std::vector<HxPlan> cands;
-    for (int py = 1; py <= 2; ++py)
+    for (int py = 1; py <= 4; ++py)
       for (int nyg = 1; nx * nyg <= hx_max_threads(py); ++nyg) {
         if (py * nyg < std::min(h->radius + 1, ny) || py * nyg > ny + 2 * h->radius) continue;
         const HxPlan p = plan_hx(nx, ny, h->n[2], 1, h->radius, eb, py, nyg);
@@ -2358,14 +2367,21 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
     for (int mode : modes) {
       if (h->np_tot == 0 && mode == 0) continue;
       if (h->rec_max != mode) {
+        if (mode > 0)  // switch on the first tiling whose records fit (any tiling serves the band route)
+          for (const HxPlan& c : cands)
+            if (hx_records_fit(h, c)) {
+              h->hx_plan = c;
+              break;
+            }
         try {
           set_projector_route(h, mode);
         } catch (const Error& e) {
-          if (mode == 0 && e.status == CHEFSI_ERR_INVALID_ARG) continue;  // no band route for this handle
+          if (e.status == CHEFSI_ERR_INVALID_ARG) continue;  // this route cannot serve this handle
           throw;
         }
       }
       for (size_t c = 0; c < cands.size(); ++c) {
+        if (h->np_tot > 0 && mode > 0 && !hx_records_fit(h, cands[c])) continue;  // tile too tall for the records
         if (h->np_tot > 0)
           build_hx_records(h, cands[c]);
         else
@@ -2385,6 +2401,8 @@ int chefsi_autotune(chefsi_handle_t* h, const void* X, int32_t ns, void* ws, siz
       }
     }
     h->prof_on = prof;
+    check(best < 1e30f, "no stencil tiling fits the projector records of this handle");
+    h->hx_plan = cands[best_c];  // a route switch builds its records for the chosen tiling
     if (h->rec_max != best_mode) set_projector_route(h, best_mode);
     if (h->np_tot > 0)
       build_hx_records(h, cands[best_c]);

@@ -195,7 +195,7 @@ __device__ __forceinline__ void halo_slot(int e, int nx, int ny, int ty, int y0,
 }
 
 // one row per thread fits 128 VGPRs, so its blocks may hold 1024 threads (taller tiles,
-// fewer halo rows per output row); two rows per thread keep 256 VGPRs and 512.
+// fewer halo rows per output row); two to four rows per thread keep 256 VGPRs and 512.
 //
 // The plane loop is kept free of divergent branches and of per-plane index arithmetic:
 // every lane writes its LDS slots unconditionally (a lane with nothing to stage writes a
@@ -484,9 +484,12 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   bool best_tall = false;
   const double big_block = elem_bytes == 8 ? 1.2 : 1.35;
   const double two_rows = elem_bytes == 8 ? 1.3 : 1.2;
-  const int pys[] = {1, 2};  // register queue budget (measured: three or four rows lose occupancy)
+  // Three or four rows per thread are reached by an explicit tiling or the timed autotune
+  // only: the cost model was fitted to one and two (in FP32 three rows measured 2-7% faster
+  // on the 72^3 and 120^3 mixed filters; in FP64 their register queue costs occupancy).
+  const int pys[] = {1, 2, 3, 4};
   for (int py : pys) {
-    if (py_override > 0 && py != py_override) continue;
+    if (py_override > 0 ? py != py_override : py > 2) continue;
     for (int nyg = 1; nx * nyg <= hx_max_threads(py); ++nyg) {
       if (nyg_override > 0 && nyg != nyg_override) continue;
       const int ty = nyg * py;
@@ -568,6 +571,8 @@ static hipError_t launch_r(const HxArgs<TI, TC, TO>& a, const HxPlan& p, int ns,
   switch (p.py) {
     case 1: return launch_rp<TI, TC, TO, R, 1>(a, p, ns, s);
     case 2: return launch_rp<TI, TC, TO, R, 2>(a, p, ns, s);
+    case 3: return launch_rp<TI, TC, TO, R, 3>(a, p, ns, s);
+    case 4: return launch_rp<TI, TC, TO, R, 4>(a, p, ns, s);
     default: return hipErrorInvalidValue;
   }
 }

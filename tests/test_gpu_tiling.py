@@ -2,7 +2,8 @@
 
 The planner picks rows per thread (PY) and halo values per thread (KH) from the grid
 shape; the largest workloads run variants (two rows per thread, four halo values) that
-small default grids never select.  chefsi_set_stencil_tiling forces each variant on a
+small default grids never select, and autotune also times three and four rows per thread,
+which the untuned planner never picks.  chefsi_set_stencil_tiling forces each variant on a
 grid small enough for the oracle, for both element types, for H X alone, for the
 refinement's FP64 product of an FP32 block, and for a whole mixed solve.  The variants
 agree with each other to rounding (the compiler contracts multiply-adds differently per
@@ -21,9 +22,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # (rows per thread, row groups): with nx = 40 and r = 6 these give KH = 4, 3 and 2 staged
-# values per thread for both PY = 1 and PY = 2 (the staged set of a tile of ty rows is
-# 2r (nx + 2r) halo-row values plus 2r ty periodic x copies, spread over the block's lanes)
-TILINGS = [(1, 4), (1, 8), (1, 24), (2, 4), (2, 6), (2, 12)]
+# values per thread for both PY = 1 and PY = 2, and KH = 4 and 3 for PY = 3, 4 for PY = 4
+# (the staged set of a tile of ty rows is 2r (nx + 2r) halo-row values plus 2r ty periodic
+# x copies, spread over the block's lanes)
+TILINGS = [(1, 4), (1, 8), (1, 24), (2, 4), (2, 6), (2, 12), (3, 4), (3, 8), (4, 6)]
 GRIDS = [((40, 24, 16), (0, 0, 0)), ((40, 23, 18), (0, 1, 1))]
 
 
@@ -67,7 +69,7 @@ def test_apply_h_every_tiling(cs, grid, prec):
         assert np.abs(got - ref).max() <= tol
         seen.add((t[0], t[3]))
         outs.append(got)
-    assert {(1, 2), (1, 3), (1, 4), (2, 2), (2, 3), (2, 4)} <= seen
+    assert {(1, 2), (1, 3), (1, 4), (2, 2), (2, 3), (2, 4), (3, 3), (3, 4), (4, 4)} <= seen
     for o in outs[1:]:
         assert np.abs(o - outs[0]).max() <= (1e-13 if prec == "fp64" else 1e-6) * scale
     h.chefsi_set_stencil_tiling(0, 0)
@@ -232,5 +234,48 @@ def test_point_in_too_many_supports_keeps_the_record_route(cs):
     py, nyg, in_stencil = h.chefsi_autotune(dev(x), ns, ws)
     print(f"autotune on the crowded grid: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
     assert in_stencil
+    check()
+    h.close()
+
+
+def test_autotune_skips_tilings_too_tall_for_the_records(cs):
+    """900 atoms x 4 projectors on a 64 x 32 x 16 grid: the block's projector row (3600
+    coefficients) leaves no LDS for the records of the tallest four-rows-per-thread tiles.
+    Asking for such a tiling on the record route is refused (the tiling is kept); autotune
+    times only the tilings that fit each route and ends with H X still the oracle's; on the
+    band pass the tall tiling is accepted, and the record route is then refused with the
+    handle left on the band pass."""
+    prob = inputs.small_problem(n=(64, 32, 16), h=(0.3, 0.3, 0.3), bc=(0, 0, 0), fd_order=12, n_atoms=900,
+                                nproj_per_atom=4, seed=3)
+    assert int(prob.nproj.sum()) == 3600
+    ns = 4
+    X = np.random.default_rng(10).standard_normal((prob.nd, ns)).astype(np.float32)
+    ref = apply_h(prob, X.astype(np.float64))
+    tol = 2e-6 * stencil_scale(prob) * np.abs(X).max() + 1e-5 * np.abs(ref).max()
+    h = cs.Handle(prob, precision=cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+
+    def check():
+        Y = torch.zeros((ns, prob.nd), dtype=torch.float32, device="cuda")
+        h.chefsi_apply_h(dev(X, "float32"), Y, ns, ws)
+        torch.cuda.synchronize()
+        err = np.abs(host(Y) - ref).max()
+        assert err <= tol, (err, tol)
+
+    default = h.chefsi_get_stencil_tiling()
+    for tall in ((4, 8), (4, 7)):
+        with pytest.raises(cs.ChefsiError, match="does not fit in LDS"):
+            h.chefsi_set_stencil_tiling(*tall)
+        assert h.chefsi_get_stencil_tiling() == default
+    check()
+    py, nyg, in_stencil = h.chefsi_autotune(dev(X, "float32"), ns, ws)
+    print(f"autotune with 3600 projectors: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
+    check()
+    h.chefsi_set_projector_pass(False)
+    h.chefsi_set_stencil_tiling(4, 8)
+    check()
+    with pytest.raises(cs.ChefsiError, match="does not fit in LDS"):
+        h.chefsi_set_projector_pass(True)
+    assert h.chefsi_get_stencil_tiling()[:2] == (4, 8)
     check()
     h.close()
