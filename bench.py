@@ -55,6 +55,9 @@ def parse():
     p.add_argument("--serving-requests", type=int, default=48, help="requests of the serving record")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="after the timed steps, run one plain device copy of 1 GiB (counter calibration)")
+    p.add_argument("--fixed-stencil", default=None, metavar="PY,GROUPS,IN_STENCIL",
+                   help="set this stencil tiling and projector route instead of timing the candidates "
+                        "(every run of the invocation; for counter passes that must profile one kernel)")
     return p.parse_args()
 
 
@@ -169,6 +172,9 @@ def initial_device_block(prob, cfg, tdt, x0):
     return X if tdt == torch.float32 else X.to(tdt)
 
 
+FIXED_STENCIL = None  # (rows per thread, row groups, projectors in the stencil pass) from --fixed-stencil
+
+
 def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
     """Time `steps` CheFSI steps of one precision on the workload; per-kernel HIP-event times."""
     import torch
@@ -184,7 +190,12 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
     stream = torch.cuda.current_stream()
     # one-time set-up: stencil tiling and projector split picked by timing (X is not changed)
     t_tune = time.perf_counter()
-    tuned = h.chefsi_autotune(X, ns, ws, stream=stream)
+    if FIXED_STENCIL is None:
+        tuned = h.chefsi_autotune(X, ns, ws, stream=stream)
+    else:
+        h.chefsi_set_projector_pass(bool(FIXED_STENCIL[2]))
+        h.chefsi_set_stencil_tiling(FIXED_STENCIL[0], FIXED_STENCIL[1])
+        tuned = FIXED_STENCIL
     tune_s = time.perf_counter() - t_tune
     for _ in range(warmup):
         d = h.chefsi_step(X, ns, m, lo, cut, hi, ws, stream=stream)
@@ -228,7 +239,7 @@ def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
                                 kern["rotate"]["ms_per_step"], prec == cs.FP64)}
     out["ritz_steps"] = ritz_steps
     out["stencil_choice"] = {"rows_per_thread": tuned[0], "row_groups": tuned[1], "projectors_in_stencil": tuned[2],
-                             "autotune_s": tune_s}
+                             "autotune_s": tune_s if FIXED_STENCIL is None else None}
     out["fallback_steps"] = int(round(fallback_steps))
     if refine_ms is not None:
         out["refine_ms"] = refine_ms
@@ -483,7 +494,11 @@ def serving_record(args, n_req: int):
 
 
 def main():
+    global FIXED_STENCIL
     args = parse()
+    if args.fixed_stencil:
+        FIXED_STENCIL = tuple(int(v) for v in args.fixed_stencil.split(","))
+        assert len(FIXED_STENCIL) == 3, "--fixed-stencil takes PY,GROUPS,IN_STENCIL"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is design only",
               file=sys.stderr)
