@@ -111,7 +111,12 @@ typedef struct {
  * the ns of later calls.  precision selects the element type of X and the
  * arithmetic of filtering/projection/rotation; the dense stage is always FP64.
  * Returns CHEFSI_ERR_INVALID_ARG on inconsistent input (including a support
- * index outside the grid or not strictly increasing). */
+ * index outside the grid or not strictly increasing), or with more than 65535
+ * projectors in all.  The projector term starts in the stencil pass (records; see
+ * chefsi_set_projector_pass) unless the projectors are too many for the block's
+ * coefficient row to fit in LDS beside the default tile (about 5000 at nx = 120):
+ * the handle then starts on the band pass, and is refused only when a grid point also
+ * lies in more than 128 projector supports. */
 int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
                   int32_t precision, int32_t max_ns, chefsi_handle_t** out);
 

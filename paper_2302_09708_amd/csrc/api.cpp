@@ -1531,6 +1531,16 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       h->pt_col = std::move(eproj);
       h->pt_val = std::move(eval);
       check(h->np_tot < 65536, "more than 65535 projectors");
+      // the record route keeps the block's projector row and partial sums in LDS beside the
+      // tile; a handle with more projectors than that leaves room for starts on the band pass
+      if (!hx_records_fit(h, h->hx_plan)) {
+        try {
+          build_band_tables(h);
+        } catch (const Error& e) {
+          throw Error{e.status, "too many projectors for the stencil pass (alpha row does not fit in LDS), and " + e.msg};
+        }
+        h->rec_max = 0;
+      }
       build_hx_records(h, h->hx_plan);
       build_scatter_records(h);
       h->supp_off = upload(h, soff.data(), soff.size());

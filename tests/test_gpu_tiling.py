@@ -279,3 +279,42 @@ def test_autotune_skips_tilings_too_tall_for_the_records(cs):
     assert h.chefsi_get_stencil_tiling()[:2] == (4, 8)
     check()
     h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_many_projectors_start_on_the_band_pass(cs, prec):
+    """1700 atoms x 4 projectors on a 120 x 120 x 40 slab: the block's coefficient row (6800
+    values) leaves no LDS for the record route beside the default tile of a 120-wide grid, so
+    the handle starts on the band pass (at most 14 atoms share a point) with H X the oracle's,
+    and asking for the record route on that tile is refused.  Autotune then times the
+    tilings that fit each route: in FP64 no tile leaves room for the records (it stays on the
+    band pass); in FP32 a 7-row tile does, and either route may win."""
+    prob = inputs.small_problem(n=(120, 120, 40), h=(0.3, 0.3, 0.3), bc=(0, 0, 1), fd_order=12, n_atoms=1700,
+                                nproj_per_atom=4, seed=41)
+    assert int(prob.nproj.sum()) == 6800
+    ns = 2
+    dt = "float64" if prec == "fp64" else "float32"
+    X = np.random.default_rng(12).standard_normal((prob.nd, ns)).astype(dt)
+    ref = apply_h(prob, X.astype(np.float64))
+    scale = stencil_scale(prob) * np.abs(X).max()
+    tol = 1e-12 * scale if prec == "fp64" else 2e-6 * scale + 1e-5 * np.abs(ref).max()
+    h = cs.Handle(prob, precision=cs.FP64 if prec == "fp64" else cs.MIXED, max_ns=ns)
+    ws = cs.workspace(h, ns)
+
+    def check():
+        Y = torch.zeros((ns, prob.nd), dtype=getattr(torch, dt), device="cuda")
+        h.chefsi_apply_h(dev(X, dt), Y, ns, ws)
+        torch.cuda.synchronize()
+        err = np.abs(host(Y) - ref).max()
+        assert err <= tol, (err, tol)
+
+    check()
+    with pytest.raises(cs.ChefsiError, match="does not fit in LDS"):
+        h.chefsi_set_projector_pass(True)
+    check()
+    py, nyg, in_stencil = h.chefsi_autotune(dev(X, dt), ns, ws)
+    print(f"{prec}, 6800 projectors: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
+    if prec == "fp64":
+        assert not in_stencil
+    check()
+    h.close()
