@@ -61,9 +61,12 @@ def parse():
     return p.parse_args()
 
 
-def kernel_source_hash(name: str) -> str:
-    path = os.path.join(ROOT, "paper_2302_09708_amd", "csrc", name)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def kernel_source_hash(*names: str) -> str:
+    """First 16 hex digits of the SHA-256 of the named csrc files, concatenated in order."""
+    h = hashlib.sha256()
+    for name in names:
+        h.update(open(os.path.join(ROOT, "paper_2302_09708_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(prob, cfg, ns_cols: int):
@@ -544,7 +547,7 @@ def main():
         # each other can differ from box to box)
         t = json.load(open(TRAFFIC_FILE))
         sc = main_run["stencil_choice"]
-        if t.get("source_sha256_16") == kernel_source_hash("hx_apply.hip"):
+        if t.get("source_sha256_16") == kernel_source_hash("hx_apply.hip", "common.h"):
             for e in t.get("entries", []):
                 if all(e["stencil_choice"].get(k) == sc[k]
                        for k in ("rows_per_thread", "row_groups", "projectors_in_stencil")):

@@ -63,11 +63,18 @@ struct HxArgs {
   int pitch;        // LDS row pitch in elements (hx_pitch)
 };
 
-// LDS row pitch of the stencil tile: nx plus a gap of at least 2r columns (the x halo) that
-// is a whole multiple of 256 bytes of elements, so the lanes of a wave that straddle two
-// tile rows fall on distinct LDS banks (a gap of 2r alone put them two to a bank).
-__host__ __device__ inline int hx_pitch(int nx, int radius, int elem_bytes) {
+// LDS row pitch of the stencil tile: at least nx + 2r (the x halo).  A wave covers whole
+// x rows of consecutive row groups, and the rows of neighbouring groups lie py rows apart,
+// so the lanes of a wave that straddles two groups fall on distinct LDS banks when
+// py * pitch = nx modulo the 256 bytes the banks span (each lane then reads the 8- or
+// 4-byte slot after its predecessor's).  The smallest such pitch is taken; when none
+// exists (py even and nx odd) nx plus a whole multiple of 256 bytes, which satisfies it
+// for one row per thread.
+__host__ __device__ inline int hx_pitch(int nx, int radius, int elem_bytes, int py) {
   const int g = 256 / elem_bytes;
+  const int base = nx + 2 * radius;
+  for (int p = base; p < base + g; ++p)
+    if (((py * p - nx) % g + g) % g == 0) return p;
   return nx + ((2 * radius + g - 1) / g) * g;
 }
 

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(hx_max_threads(PY)) void hx_apply_kernel(HxArgs<TI,
 }
 
 size_t hx_lds_bytes(const HxPlan& p, int nx, int radius, int elem_bytes, int np_tot, int acc_bytes) {
-  size_t lds = 2 * ((size_t)(p.ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes) + kHxDummy) * elem_bytes;
+  size_t lds = 2 * ((size_t)(p.ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes, p.py) + kHxDummy) * elem_bytes;
   if (np_tot >= 0) {
     lds += (size_t)((p.zc + 1 + 3) & ~3) * sizeof(int);
     lds += (size_t)((np_tot + 1) & ~1) * acc_bytes;
@@ -499,7 +499,7 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
       // staged values per thread bound (counted for a periodic x, the larger set)
       const int nslots = hx_halo_slots(nx, ty, radius, 1);
       if (nslots > kHxMaxHalo * waves * 64) continue;
-      const size_t lds = 2 * ((size_t)(ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes) + kHxDummy) * elem_bytes;
+      const size_t lds = 2 * ((size_t)(ty + 2 * radius) * hx_pitch(nx, radius, elem_bytes, py) + kHxDummy) * elem_bytes;
       if (lds > 48 * 1024) continue;
       const double lane_eff = (double)threads / (waves * 64.0);
       const double row_eff = (double)ny / (nty * ty);
@@ -542,7 +542,7 @@ static hipError_t launch_final(const HxArgs<TI, TC, TO>& a0, const HxPlan& p, in
   a.zc = p.zc;
   a.nzc = p.nzc;
   a.nblocks = (int64_t)p.nty * p.nzc * ns;
-  a.pitch = hx_pitch(a.nx, R, (int)sizeof(TI));
+  a.pitch = hx_pitch(a.nx, R, (int)sizeof(TI), PY);
   a.per_xcd = (int)((a.nblocks + 7) / 8);
   const size_t lds = hx_lds_bytes(p, a.nx, R, (int)sizeof(TI), NL ? a.np_tot : -1, (int)sizeof(TC));
   if (lds > kHxMaxLds) return hipErrorInvalidConfiguration;

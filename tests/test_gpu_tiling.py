@@ -239,15 +239,15 @@ def test_point_in_too_many_supports_keeps_the_record_route(cs):
 
 
 def test_autotune_skips_tilings_too_tall_for_the_records(cs):
-    """900 atoms x 4 projectors on a 64 x 32 x 16 grid: the block's projector row (3600
+    """1800 atoms x 4 projectors on a 64 x 64 x 32 grid: the block's projector row (7200
     coefficients) leaves no LDS for the records of the tallest four-rows-per-thread tiles.
     Asking for such a tiling on the record route is refused (the tiling is kept); autotune
     times only the tilings that fit each route and ends with H X still the oracle's; on the
     band pass the tall tiling is accepted, and the record route is then refused with the
     handle left on the band pass."""
-    prob = inputs.small_problem(n=(64, 32, 16), h=(0.3, 0.3, 0.3), bc=(0, 0, 0), fd_order=12, n_atoms=900,
+    prob = inputs.small_problem(n=(64, 64, 32), h=(0.3, 0.3, 0.3), bc=(0, 0, 0), fd_order=12, n_atoms=1800,
                                 nproj_per_atom=4, seed=3)
-    assert int(prob.nproj.sum()) == 3600
+    assert int(prob.nproj.sum()) == 7200
     ns = 4
     X = np.random.default_rng(10).standard_normal((prob.nd, ns)).astype(np.float32)
     ref = apply_h(prob, X.astype(np.float64))
@@ -269,7 +269,7 @@ def test_autotune_skips_tilings_too_tall_for_the_records(cs):
         assert h.chefsi_get_stencil_tiling() == default
     check()
     py, nyg, in_stencil = h.chefsi_autotune(dev(X, "float32"), ns, ws)
-    print(f"autotune with 3600 projectors: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
+    print(f"autotune with 7200 projectors: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
     check()
     h.chefsi_set_projector_pass(False)
     h.chefsi_set_stencil_tiling(4, 8)
@@ -283,12 +283,12 @@ def test_autotune_skips_tilings_too_tall_for_the_records(cs):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_many_projectors_start_on_the_band_pass(cs, prec):
-    """1700 atoms x 4 projectors on a 120 x 120 x 40 slab: the block's coefficient row (6800
-    values) leaves no LDS for the record route beside the default tile of a 120-wide grid, so
-    the handle starts on the band pass (at most 14 atoms share a point) with H X the oracle's,
-    and asking for the record route on that tile is refused.  Autotune then times the
-    tilings that fit each route: in FP64 no tile leaves room for the records (it stays on the
-    band pass); in FP32 a 7-row tile does, and either route may win."""
+    """1700 atoms x 4 projectors on a 120 x 120 x 40 slab (at most 14 atoms share a point).
+    In FP64 the block's coefficient row (6800 values) leaves no LDS for the record route
+    beside any tile of a 120-wide grid: the handle starts on the band pass with H X the
+    oracle's, asking for the record route is refused, and autotune stays on the band pass.
+    In FP32 the tiles are small enough for the records: the handle starts on the record
+    route and autotune may pick either; H X is the oracle's throughout."""
     prob = inputs.small_problem(n=(120, 120, 40), h=(0.3, 0.3, 0.3), bc=(0, 0, 1), fd_order=12, n_atoms=1700,
                                 nproj_per_atom=4, seed=41)
     assert int(prob.nproj.sum()) == 6800
@@ -309,9 +309,10 @@ def test_many_projectors_start_on_the_band_pass(cs, prec):
         assert err <= tol, (err, tol)
 
     check()
-    with pytest.raises(cs.ChefsiError, match="does not fit in LDS"):
-        h.chefsi_set_projector_pass(True)
-    check()
+    if prec == "fp64":
+        with pytest.raises(cs.ChefsiError, match="does not fit in LDS"):
+            h.chefsi_set_projector_pass(True)
+        check()
     py, nyg, in_stencil = h.chefsi_autotune(dev(X, dt), ns, ws)
     print(f"{prec}, 6800 projectors: rows {py} x groups {nyg}, records {in_stencil}", flush=True)
     if prec == "fp64":
