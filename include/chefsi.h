@@ -114,9 +114,9 @@ typedef struct {
  * index outside the grid or not strictly increasing), or with more than 65535
  * projectors in all.  The projector term starts in the stencil pass (records; see
  * chefsi_set_projector_pass) unless the projectors are too many for the block's
- * coefficient row to fit in LDS beside the default tile (about 5000 at nx = 120):
- * the handle then starts on the band pass, and is refused only when a grid point also
- * lies in more than 128 projector supports. */
+ * coefficient row to fit in LDS beside the default tile (in FP64 about 5000 on a grid
+ * 120 points wide): the handle then starts on the band pass, and is refused only when a
+ * grid point also lies in more than 128 projector supports. */
 int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chefsi_nonlocal_t* nl,
                   int32_t precision, int32_t max_ns, chefsi_handle_t** out);
 
@@ -167,9 +167,9 @@ int chefsi_set_stencil_tiling(chefsi_handle_t* h, int32_t rows_per_thread, int32
  * next).  A grid point inside more than 128 projector supports fits no region: the band
  * pass is then refused with CHEFSI_ERR_INVALID_ARG and the handle stays on the record
  * route; the record route is refused, the handle staying on the band pass, when the
- * current tiling leaves no LDS for its records.  Rebuilds the handle's tables (the band pass holds partial sums for max_ns
- * orbitals on the device); for tuning and tests, not while calls on the handle are in
- * flight. */
+ * current tiling leaves no LDS for its records.  Rebuilds the handle's tables (the band
+ * pass holds partial sums for max_ns orbitals on the device); for tuning and tests, not
+ * while calls on the handle are in flight. */
 int chefsi_set_projector_pass(chefsi_handle_t* h, int32_t in_stencil);
 
 /* Picks the stencil tiling and the projector split by timing them (the planner's

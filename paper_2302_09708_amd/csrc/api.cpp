@@ -1532,7 +1532,8 @@ int chefsi_create(const chefsi_grid_t* grid, const double* veff_host, const chef
       h->pt_val = std::move(eval);
       check(h->np_tot < 65536, "more than 65535 projectors");
       // the record route keeps the block's projector row and partial sums in LDS beside the
-      // tile; a handle with more projectors than that leaves room for starts on the band pass
+      // tile; a handle whose projectors overflow that budget for the default tile starts on
+      // the band pass
       if (!hx_records_fit(h, h->hx_plan)) {
         try {
           build_band_tables(h);

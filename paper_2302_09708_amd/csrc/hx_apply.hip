@@ -486,7 +486,8 @@ HxPlan plan_hx(int nx, int ny, int nz, int ns, int radius, int elem_bytes, int p
   const double two_rows = elem_bytes == 8 ? 1.3 : 1.2;
   // Three or four rows per thread are reached by an explicit tiling or the timed autotune
   // only: the cost model was fitted to one and two (in FP32 three rows measured 2-7% faster
-  // on the 72^3 and 120^3 mixed filters; in FP64 their register queue costs occupancy).
+  // on the 72^3 and 60x60x180 mixed filters, four at 120^3; in FP64 their register queue
+  // costs occupancy).
   const int pys[] = {1, 2, 3, 4};
   for (int py : pys) {
     if (py_override > 0 ? py != py_override : py > 2) continue;
