@@ -55,6 +55,9 @@ def parse():
     p.add_argument("--serving-requests", type=int, default=48, help="requests of the serving record")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="after the timed steps, run one plain device copy of 1 GiB (counter calibration)")
+    p.add_argument("--gemm-probe", action="store_true",
+                   help="only the mixed handle's projection and rotation on the workload's block sizes (no "
+                        "dense stage): prints their times and MFMA rates, for counter runs of the split-bf16 kernels")
     p.add_argument("--fixed-stencil", default=None, metavar="PY,GROUPS,IN_STENCIL",
                    help="set this stencil tiling and projector route instead of timing the candidates "
                         "(every run of the invocation; for counter passes that must profile one kernel)")
@@ -176,6 +179,47 @@ def initial_device_block(prob, cfg, tdt, x0):
 
 
 FIXED_STENCIL = None  # (rows per thread, row groups, projectors in the stencil pass) from --fixed-stencil
+
+
+def gemm_probe(args):
+    """The mixed handle's projection (Hs = X^T H X, Ms = X^T X: one stencil pass and the two
+    split-bf16 Gram products) and rotation (X <- X Z, Z the identity, so X stays bounded) on
+    the workload's Nd x Ns block drawn on the device, `steps` times after one warm-up each,
+    timed by the library's HIP events.  No dense stage: for hardware-counter runs of the
+    split-bf16 kernels at sizes whose full step cannot run under the counter profiler."""
+    import torch
+    from paper_2302_09708_amd import chefsi as cs
+    from paper_2302_09708_amd import inputs
+    cs.load()
+    cfg = inputs.CONFIGS[args.workload]
+    prob = inputs.make_problem(cfg)
+    ns = cfg.ns
+    h = cs.Handle(prob, precision=cs.MIXED, max_ns=ns)
+    X = initial_device_block(prob, cfg, torch.float32, None)
+    ws = cs.workspace(h, ns)
+    Hs = torch.empty(ns * ns, dtype=torch.float64, device="cuda")
+    Ms = torch.empty_like(Hs)
+    Z = torch.eye(ns, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    h.chefsi_project(X, ns, Hs, Ms, ws, stream=stream)
+    h.chefsi_rotate(X, Z, ns, ws, stream=stream)
+    torch.cuda.synchronize()
+    h.chefsi_profile_enable(True)
+    h.chefsi_profile_reset()
+    for i in range(args.steps):
+        h.chefsi_project(X, ns, Hs, Ms, ws, stream=stream)
+        h.chefsi_rotate(X, Z, ns, ws, stream=stream)
+        print(f"[gemm-probe] {cfg.name} call {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    kern = {}
+    for kid, name in enumerate(KERNELS):
+        ms, n = h.chefsi_profile_read(kid)
+        kern[name] = ms / args.steps
+    h.chefsi_profile_enable(False)
+    g = gemm_figures(prob.nd, ns, cs.MIXED, kern["gram"] + kern["gram_reduce"], kern["rotate"], False)
+    print(json.dumps({"mode": "gemm_probe", "workload": cfg.name, "nd": prob.nd, "ns": ns, "calls": args.steps,
+                      "ms_per_call": {k: v for k, v in kern.items() if v > 0}, "gemm": g}))
+    h.close()
 
 
 def run_path(cs, prob, cfg, precision: str, steps: int, warmup: int, x0):
@@ -508,6 +552,9 @@ def main():
         sys.exit(2)
     if args.workload == "cfg5":
         serving_bench(args)
+        return
+    if args.gemm_probe:
+        gemm_probe(args)
         return
     import torch
     from paper_2302_09708_amd import chefsi as cs
